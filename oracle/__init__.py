@@ -1,0 +1,203 @@
+"""MacLAB oracle: ctypes binding of the plain FP64 C implementation.
+
+Test infrastructure only. The test suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only users; the GPU library never imports,
+links or executes anything here, and nothing here imports the GPU library.
+
+Every function mirrors one step of the paper (Zhou, arXiv:1901.02716):
+
+* :func:`lattice` -- D2Q9 / D3Q19 velocity sets and weights (main text,
+  with Eqs. (1)-(2); D3Q19 at the start of the numerical tests).
+* :func:`feq` -- the local equilibrium, Eq. (2) [feq-full].
+* :func:`particle_speed`, :func:`time_step` -- Eq. (6) [mlb-viscosity] and
+  dt = dx/e.
+* :func:`run` -- repeated application of Eqs. (4)-(5) [mlb-p.1, mlb-u.1] with
+  fixed (Dirichlet) and periodic faces and the body-force term of test 2.
+* :func:`diagnostics` -- mass, momentum, kinetic energy, max |u|/e and the
+  non-finite count (the conserved moments of Methods, Eqs. (14)-(15)).
+* :func:`adjoint_run` -- reverse-mode derivative of :func:`run` for a
+  squared-error loss on the final velocity.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "maclab_oracle.c")
+_LIB = os.path.join(_HERE, "libmaclab_oracle.so")
+
+PERIODIC = 0
+FIXED = 1
+FACES = ("xlo", "xhi", "ylo", "yhi", "zlo", "zhi")
+
+
+def build(force: bool = False, extra_flags: tuple[str, ...] = (), out: str | None = None) -> str:
+    """Compiles the oracle with gcc (single thread, no FMA contraction)."""
+    out = out or _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+               *extra_flags, _SRC, "-o", out, "-lm"]
+        subprocess.run(cmd, check=True)
+    return out
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("q", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("n", ctypes.c_int64 * 3),
+        ("dx", ctypes.c_double),
+        ("nu", ctypes.c_double),
+        ("G", ctypes.c_double * 3),
+        ("face_kind", ctypes.c_int32 * 6),
+        ("face_rho", ctypes.c_double * 6),
+        ("face_u", (ctypes.c_double * 3) * 6),
+    ]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_libs: dict[str, ctypes.CDLL] = {}
+_active: str | None = None
+
+
+def use(path: str | None) -> str | None:
+    """Makes `path` the library every call uses (None: the default build).
+
+    Returns the previous choice. Tests use this to run the pins against
+    deliberately broken builds of the oracle.
+    """
+    global _active
+    prev, _active = _active, path
+    return prev
+
+
+def load(path: str | None = None) -> ctypes.CDLL:
+    path = path or _active or build()
+    if path not in _libs:
+        lib = ctypes.CDLL(path)
+        lib.oracle_lattice.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), _dp]
+        lib.oracle_particle_speed.restype = ctypes.c_double
+        lib.oracle_particle_speed.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.oracle_time_step.restype = ctypes.c_double
+        lib.oracle_time_step.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.oracle_feq.restype = ctypes.c_double
+        lib.oracle_feq.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, ctypes.c_double]
+        lib.oracle_impose_boundary.argtypes = [ctypes.POINTER(_Problem), _dp, _dp]
+        lib.oracle_run.argtypes = [ctypes.POINTER(_Problem), _dp, _dp, ctypes.c_int64]
+        lib.oracle_diagnostics.argtypes = [ctypes.POINTER(_Problem), _dp, _dp, _dp]
+        if hasattr(lib, "oracle_adjoint_run"):
+            lib.oracle_adjoint_run.argtypes = [ctypes.POINTER(_Problem), _dp, _dp, ctypes.c_int64,
+                                               _dp, _dp, _dp, _dp]
+        _libs[path] = lib
+    return _libs[path]
+
+
+@dataclass
+class Problem:
+    """Lattice, node counts, dx, nu, body force and per-face boundaries."""
+
+    q: int
+    n: tuple[int, int, int]
+    dx: float
+    nu: float
+    G: tuple[float, float, float] = (0.0, 0.0, 0.0)
+    face_kind: list[int] = field(default_factory=lambda: [PERIODIC] * 6)
+    face_rho: list[float] = field(default_factory=lambda: [1.0] * 6)
+    face_u: list[tuple[float, float, float]] = field(default_factory=lambda: [(0.0, 0.0, 0.0)] * 6)
+
+    @property
+    def d(self) -> int:
+        return 2 if self.q == 9 else 3
+
+    @property
+    def N(self) -> int:
+        return int(self.n[0]) * int(self.n[1]) * int(self.n[2])
+
+    def set_fixed(self, face: str | int, rho: float, u) -> "Problem":
+        f = FACES.index(face) if isinstance(face, str) else int(face)
+        self.face_kind[f] = FIXED
+        self.face_rho[f] = float(rho)
+        uu = tuple(float(v) for v in u) + (0.0,) * (3 - len(u))
+        self.face_u[f] = uu[:3]
+        return self
+
+    def _c(self) -> _Problem:
+        p = _Problem()
+        p.q = self.q
+        for i in range(3):
+            p.n[i] = int(self.n[i])
+            p.G[i] = float(self.G[i])
+        p.dx = float(self.dx)
+        p.nu = float(self.nu)
+        for f in range(6):
+            p.face_kind[f] = int(self.face_kind[f])
+            p.face_rho[f] = float(self.face_rho[f])
+            for c in range(3):
+                p.face_u[f][c] = float(self.face_u[f][c])
+        return p
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_dp)
+
+
+def lattice(q: int):
+    """Returns (c [q,3] int, w [q] float64) in the paper's order."""
+    c = (ctypes.c_int * (3 * q))()
+    w = np.zeros(q)
+    if load().oracle_lattice(q, c, _ptr(w)) != 0:
+        raise ValueError(f"unknown lattice q={q}")
+    return np.array(list(c), dtype=np.int64).reshape(q, 3), w
+
+
+def particle_speed(nu: float, dx: float) -> float:
+    return load().oracle_particle_speed(nu, dx)
+
+
+def time_step(nu: float, dx: float) -> float:
+    return load().oracle_time_step(nu, dx)
+
+
+def feq(q: int, a: int, rho: float, u, e: float) -> float:
+    uu = np.zeros(3)
+    uu[: len(u)] = u
+    return load().oracle_feq(q, a, rho, _ptr(uu), e)
+
+
+def impose_boundary(p: Problem, rho: np.ndarray, u: np.ndarray) -> None:
+    if load().oracle_impose_boundary(ctypes.byref(p._c()), _ptr(rho), _ptr(u)) != 0:
+        raise ValueError("invalid problem")
+
+
+def run(p: Problem, rho0: np.ndarray, u0: np.ndarray, steps: int, lib: str | None = None):
+    """Advances copies of (rho0, u0) by `steps` MacLAB steps.
+
+    rho0 has shape (N,) or the grid shape; u0 has d planes. Boundary values of
+    fixed faces are imposed first. Returns (rho, u) with the input shapes.
+    """
+    rho = np.ascontiguousarray(rho0, dtype=np.float64).copy()
+    u = np.ascontiguousarray(u0, dtype=np.float64).copy()
+    assert rho.size == p.N and u.size == p.d * p.N
+    L = load(lib)
+    c = p._c()
+    if L.oracle_impose_boundary(ctypes.byref(c), _ptr(rho), _ptr(u)) != 0:
+        raise ValueError("invalid problem")
+    rc = L.oracle_run(ctypes.byref(c), _ptr(rho), _ptr(u), int(steps))
+    if rc != 0:
+        raise ValueError(f"oracle_run failed ({rc})")
+    return rho, u
+
+
+def diagnostics(p: Problem, rho: np.ndarray, u: np.ndarray) -> np.ndarray:
+    out = np.zeros(7)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    if load().oracle_diagnostics(ctypes.byref(p._c()), _ptr(rho), _ptr(u), _ptr(out)) != 0:
+        raise ValueError("invalid problem")
+    return out

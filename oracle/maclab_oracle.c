@@ -1,0 +1,301 @@
+/*
+ * MacLAB oracle: a plain, single-threaded, FP64 CPU implementation of the
+ * macroscopic lattice Boltzmann time step of J. G. Zhou, "Macroscopic
+ * Lattice Boltzmann Method (MacLAB)", arXiv:1901.02716.
+ *
+ * TEST INFRASTRUCTURE. This file is the correctness reference for the GPU
+ * library and nothing else: only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it. It shares no code, header,
+ * table or helper with the GPU path, and the GPU path never calls it.
+ *
+ * It is deliberately slow and literal. Everything is done in physical units,
+ * in the paper's notation:
+ *   e_a   = e * c_a                    particle velocity of link a
+ *   f_eq  = w_a rho (1 + 3 e_a.u/e^2 + 9/2 (e_a.u)^2/e^4 - 3/2 u.u/e^2)
+ *                                       main text, Eq. (2) [feq-full]
+ *   rho(x,t)  = sum_a f_eq_a(x - e_a dt, t - dt)        Eq. (4) [mlb-p.1]
+ *   u_i(x,t)  = 1/rho(x,t) sum_a e_ai f_eq_a(x - e_a dt, t - dt)
+ *                                                       Eq. (5) [mlb-u.1]
+ *   e  = 6 nu / dx                                      Eq. (6) [mlb-viscosity]
+ *   dt = dx / e                                         text after Eq. (6)
+ * A node x - e_a dt is the neighbouring lattice node x - c_a (main text,
+ * after Eq. (6)); periodic axes wrap (numerical tests 1, 2 and 4).
+ *
+ * Readings of the paper this file takes (each one is listed in the design
+ * notes of the repository):
+ *  - Eq. (5) sums e_{aj}; the Methods derivation, Eqs. (12)-(13), shows the
+ *    component is e_{ai}. The oracle uses e_{ai}.
+ *  - Test 2 adds a pressure-gradient term "+dx/(e rho) dp/dx" to Eq. (5).
+ *    With dp/dx < 0 that literal sign drives the flow towards -x, which
+ *    contradicts the analytic profile Eq. (8) [Couette-PreGrad]. The oracle
+ *    adds  + dt * G / rho'  with G = -dp/dx (a body force per unit volume),
+ *    using dx/e = dt; rho' is the newly gathered density.
+ *  - Fixed boundary nodes hold their physical rho and u ("no calculations
+ *    are needed", test 2; abstract, advantage (i)). A node on several fixed
+ *    faces takes the values of the face with the lowest index in the order
+ *    XLO, XHI, YLO, YHI, ZLO, ZHI (so side walls own the edges and corners
+ *    of a lid on the highest face).
+ *  - Both faces of an axis are either periodic or fixed.
+ *
+ * Build: gcc -std=c11 -O2 -ffp-contract=off -fPIC -shared (no threads, no
+ * SIMD intrinsics, no FMA contraction).
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_PERIODIC 0
+#define ORACLE_FIXED 1
+
+/* Problem statement: lattice, node counts, dx, nu (main text, recipe step
+ * (i)), a uniform body force, and per-face boundary kind and values. */
+typedef struct {
+  int32_t q;          /* 9 = D2Q9, 19 = D3Q19 */
+  int32_t reserved;
+  int64_t n[3];       /* node counts including boundary nodes; n[2] = 1 in 2D */
+  double dx;          /* lattice size [m] */
+  double nu;          /* kinematic viscosity [m^2/s] */
+  double G[3];        /* body force per unit volume, G = -grad p [N/m^3] */
+  int32_t face_kind[6];
+  double face_rho[6];
+  double face_u[6][3];
+} oracle_problem;
+
+/* ---- Lattices ------------------------------------------------------------
+ * D2Q9: velocities listed with Eq. (1) [lb.1], in that order; weights 4/9,
+ * 1/9 and 1/36 given with Eq. (2).
+ * D3Q19: velocities and weights 1/3, 1/18, 1/36 listed at the start of the
+ * numerical tests, in that order. */
+static const int D2Q9_C[9][3] = {
+    {0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
+    {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+static const double D2Q9_W[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
+                                 1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
+                                 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+static const int D3Q19_C[19][3] = {
+    {0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+    {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {-1, 1, 0},
+    {1, -1, 0}, {0, 1, 1},   {0, -1, -1}, {0, -1, 1}, {0, 1, -1},
+    {1, 0, 1},  {-1, 0, -1}, {-1, 0, 1}, {1, 0, -1}};
+static const double D3Q19_W[19] = {
+    1.0 / 3.0,  1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+    1.0 / 18.0, 1.0 / 18.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+static int lattice_dims(int q) { return q == 9 ? 2 : (q == 19 ? 3 : 0); }
+
+static const int (*lattice_c(int q))[3] { return q == 9 ? D2Q9_C : D3Q19_C; }
+
+static const double* lattice_w(int q) { return q == 9 ? D2Q9_W : D3Q19_W; }
+
+/* Copies the velocity set (q x 3 ints) and weights (q doubles) out. */
+int oracle_lattice(int q, int* c_out, double* w_out) {
+  if (lattice_dims(q) == 0) return -1;
+  const int(*c)[3] = lattice_c(q);
+  const double* w = lattice_w(q);
+  for (int a = 0; a < q; ++a) {
+    for (int i = 0; i < 3; ++i) c_out[3 * a + i] = c[a][i];
+    w_out[a] = w[a];
+  }
+  return 0;
+}
+
+/* Eq. (6) [mlb-viscosity]: particle speed from viscosity and lattice size. */
+double oracle_particle_speed(double nu, double dx) { return 6.0 * nu / dx; }
+
+/* Text after Eq. (6): the time step is no longer free, dt = dx / e. */
+double oracle_time_step(double nu, double dx) {
+  return dx / oracle_particle_speed(nu, dx);
+}
+
+/* Eq. (2) [feq-full] for link a, in physical units with e_a = e c_a. */
+double oracle_feq(int q, int a, double rho, const double* u, double e) {
+  const int(*c)[3] = lattice_c(q);
+  const double* w = lattice_w(q);
+  const int d = lattice_dims(q);
+  double eu = 0.0, uu = 0.0;
+  for (int i = 0; i < d; ++i) {
+    double ea_i = e * (double)c[a][i];
+    eu += ea_i * u[i];
+    uu += u[i] * u[i];
+  }
+  double e2 = e * e;
+  return w[a] * rho *
+         (1.0 + 3.0 * eu / e2 + 4.5 * eu * eu / (e2 * e2) - 1.5 * uu / e2);
+}
+
+/* ---- Geometry helpers ----------------------------------------------------*/
+static int validate(const oracle_problem* p) {
+  int d = lattice_dims(p->q);
+  if (d == 0) return -1;
+  if (!(p->dx > 0.0) || !(p->nu > 0.0)) return -1;
+  for (int ax = 0; ax < 3; ++ax) {
+    if (p->n[ax] < 1) return -1;
+    int lo = p->face_kind[2 * ax], hi = p->face_kind[2 * ax + 1];
+    if (lo != hi) return -1;
+    if (lo != ORACLE_PERIODIC && lo != ORACLE_FIXED) return -1;
+    if (ax >= d && (p->n[ax] != 1 || lo != ORACLE_PERIODIC)) return -1;
+    if (lo == ORACLE_FIXED && p->n[ax] < 3) return -1;
+  }
+  return 0;
+}
+
+/* Index of the lowest-numbered fixed face the node lies on, or -1. */
+static int fixed_face(const oracle_problem* p, int64_t i, int64_t j,
+                      int64_t k) {
+  const int64_t idx[3] = {i, j, k};
+  for (int f = 0; f < 6; ++f) {
+    if (p->face_kind[f] != ORACLE_FIXED) continue;
+    int ax = f / 2;
+    int64_t at = (f % 2 == 0) ? 0 : p->n[ax] - 1;
+    if (idx[ax] == at) return f;
+  }
+  return -1;
+}
+
+static int64_t wrap(int64_t v, int64_t n) {
+  int64_t r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+/* Writes the fixed-face values (rho_b, u_b) into every fixed node. */
+int oracle_impose_boundary(const oracle_problem* p, double* rho, double* u) {
+  if (validate(p)) return -1;
+  const int d = lattice_dims(p->q);
+  const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
+  const int64_t N = nx * ny * nz;
+  for (int64_t k = 0; k < nz; ++k)
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) {
+        int f = fixed_face(p, i, j, k);
+        if (f < 0) continue;
+        int64_t x = i + nx * (j + ny * k);
+        rho[x] = p->face_rho[f];
+        for (int c = 0; c < d; ++c) u[c * N + x] = p->face_u[f][c];
+      }
+  return 0;
+}
+
+/* One MacLAB step from (rho, u) into (rho_new, u_new). */
+static void step_once(const oracle_problem* p, double e, double dt,
+                      const double* rho, const double* u, double* rho_new,
+                      double* u_new) {
+  const int q = p->q, d = lattice_dims(q);
+  const int(*c)[3] = lattice_c(q);
+  const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
+  const int64_t N = nx * ny * nz;
+  for (int64_t k = 0; k < nz; ++k)
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) {
+        const int64_t x = i + nx * (j + ny * k);
+        if (fixed_face(p, i, j, k) >= 0) {
+          /* Recipe step (iv): boundary nodes keep their physical values. */
+          rho_new[x] = rho[x];
+          for (int cc = 0; cc < d; ++cc) u_new[cc * N + x] = u[cc * N + x];
+          continue;
+        }
+        double r = 0.0;
+        double m[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < q; ++a) {
+          /* Source node x - e_a dt = x - c_a. */
+          int64_t si = wrap(i - c[a][0], nx);
+          int64_t sj = wrap(j - c[a][1], ny);
+          int64_t sk = wrap(k - c[a][2], nz);
+          int64_t s = si + nx * (sj + ny * sk);
+          double us[3] = {0.0, 0.0, 0.0};
+          for (int cc = 0; cc < d; ++cc) us[cc] = u[cc * N + s];
+          double f = oracle_feq(q, a, rho[s], us, e);
+          r += f;                                     /* Eq. (4) */
+          for (int cc = 0; cc < d; ++cc) m[cc] += e * (double)c[a][cc] * f;
+        }
+        rho_new[x] = r;
+        for (int cc = 0; cc < d; ++cc) {
+          /* Eq. (5) plus the body-force term of test 2 (sign per G). */
+          u_new[cc * N + x] = m[cc] / r + dt * p->G[cc] / r;
+        }
+      }
+}
+
+/* Advances (rho, u) in place by `steps` time steps. rho has N = nx*ny*nz
+ * entries, u has d planes of N entries (component-major), x fastest.
+ * Boundary values must already be in the arrays (oracle_impose_boundary).
+ * Returns 0, or -1 on an invalid problem, -2 on allocation failure. */
+int oracle_run(const oracle_problem* p, double* rho, double* u,
+               int64_t steps) {
+  if (validate(p) || steps < 0) return -1;
+  const int d = lattice_dims(p->q);
+  const int64_t N = p->n[0] * p->n[1] * p->n[2];
+  const double e = oracle_particle_speed(p->nu, p->dx);
+  const double dt = p->dx / e;
+  double* r2 = (double*)malloc(sizeof(double) * (size_t)N);
+  double* u2 = (double*)malloc(sizeof(double) * (size_t)(N * d));
+  if (!r2 || !u2) {
+    free(r2);
+    free(u2);
+    return -2;
+  }
+  for (int64_t s = 0; s < steps; ++s) {
+    step_once(p, e, dt, rho, u, r2, u2);
+    memcpy(rho, r2, sizeof(double) * (size_t)N);
+    memcpy(u, u2, sizeof(double) * (size_t)(N * d));
+  }
+  free(r2);
+  free(u2);
+  return 0;
+}
+
+/* ---- Diagnostics ---------------------------------------------------------
+ * Mass M = sum rho, momentum P = sum rho u, kinetic energy
+ * E = 1/2 sum rho |u|^2 over all nodes (the conserved moments of the
+ * equilibrium, Methods, Eqs. (14)-(15)), the largest |u|/e (the Mach number
+ * the paper's validity condition refers to), and the number of nodes holding
+ * a non-finite value. Sums use Neumaier's compensated summation. */
+typedef struct {
+  double s, c;
+} neumaier;
+
+static void nsum_add(neumaier* a, double v) {
+  double t = a->s + v;
+  if (fabs(a->s) >= fabs(v))
+    a->c += (a->s - t) + v;
+  else
+    a->c += (v - t) + a->s;
+  a->s = t;
+}
+
+int oracle_diagnostics(const oracle_problem* p, const double* rho,
+                       const double* u, double* out7) {
+  if (validate(p)) return -1;
+  const int d = lattice_dims(p->q);
+  const int64_t N = p->n[0] * p->n[1] * p->n[2];
+  const double e = oracle_particle_speed(p->nu, p->dx);
+  neumaier M = {0, 0}, P[3] = {{0, 0}, {0, 0}, {0, 0}}, E = {0, 0};
+  double umax = 0.0, bad = 0.0;
+  for (int64_t x = 0; x < N; ++x) {
+    int finite = isfinite(rho[x]);
+    double uu = 0.0;
+    for (int c = 0; c < d; ++c) {
+      finite = finite && isfinite(u[c * N + x]);
+      uu += u[c * N + x] * u[c * N + x];
+    }
+    if (!finite) {
+      bad += 1.0;
+      continue;
+    }
+    nsum_add(&M, rho[x]);
+    for (int c = 0; c < d; ++c) nsum_add(&P[c], rho[x] * u[c * N + x]);
+    nsum_add(&E, 0.5 * rho[x] * uu);
+    double m = sqrt(uu) / e;
+    if (m > umax) umax = m;
+  }
+  out7[0] = M.s + M.c;
+  for (int c = 0; c < 3; ++c) out7[1 + c] = P[c].s + P[c].c;
+  out7[4] = E.s + E.c;
+  out7[5] = umax;
+  out7[6] = bad;
+  return 0;
+}
