@@ -1,0 +1,159 @@
+/*
+ * maclab.h -- C ABI of the MI355X (gfx950) MacLAB library.
+ *
+ * The library advances the macroscopic lattice Boltzmann method of
+ * J. G. Zhou, "Macroscopic Lattice Boltzmann Method (MacLAB)",
+ * arXiv:1901.02716: with relaxation time tau = 1 the populations after a
+ * step are the previous equilibria of the upstream neighbours (Methods,
+ * Eqs. (9)-(10)), so only the density and velocity are stored and one step is
+ *
+ *   rho(x, t) = sum_a f_eq_a(x - e_a dt, t - dt)                  Eq. (4)
+ *   u(x, t)   = 1/rho(x, t) sum_a e_a f_eq_a(x - e_a dt, t - dt)  Eq. (5)
+ *
+ * with f_eq of Eq. (2), particle speed e = 6 nu / dx (Eq. (6)) and time step
+ * dt = dx / e. A problem is stated as the paper states it (recipe steps
+ * (i)-(v) after Eq. (6)): a lattice, node counts, the lattice size dx, the
+ * viscosity nu, macroscopic boundary values and the initial rho and u.
+ *
+ * Conventions
+ *  - Every function returns an int status: MACLAB_OK (0) or a negative code.
+ *    No C++ exception crosses this interface. maclab_last_error(h) returns a
+ *    handle-owned message valid until the next call on h; with h == NULL it
+ *    returns the message of the last failed call on this thread that had no
+ *    handle (for example a rejected maclab_init).
+ *  - Fields are SoA float64 arrays in physical units: rho has N = nx*ny*nz
+ *    entries, u has d planes of N entries (u_x plane, then u_y, then u_z),
+ *    node (i, j, k) at index i + nx*(j + ny*k). d = 2 for D2Q9, 3 for D3Q19.
+ *  - Ownership: the caller owns every device buffer (including the workspace)
+ *    and the stream; the library owns only the opaque handle and never frees
+ *    caller memory. The workspace must outlive the handle.
+ *  - Ordering: calls are ordered on the configured HIP stream. Only calls that
+ *    return data to host memory (get_fields / set_fields with on_device = 0,
+ *    diagnostics, params) synchronise that stream. A handle is not
+ *    thread-safe; distinct handles are independent.
+ */
+#ifndef MACLAB_H
+#define MACLAB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define MACLAB_OK 0
+#define MACLAB_EINVAL -1       /* an argument or the configuration is invalid */
+#define MACLAB_EUNSUPPORTED -2 /* lattice / precision / shape not supported */
+#define MACLAB_EHIP -3         /* HIP runtime error; message names it */
+#define MACLAB_EWORKSPACE -4   /* workspace missing or too small */
+#define MACLAB_ENONFINITE -5   /* a checked step found NaN/Inf or |u|/e >= 1 */
+
+/* Lattices (main text: D2Q9 with Eq. (1); D3Q19 in the numerical tests). */
+enum { MACLAB_D2Q9 = 9, MACLAB_D3Q19 = 19 };
+
+/* Storage of (rho - rho_ref, u / e) between steps. Arithmetic is FP64 for
+ * MACLAB_FP64 and FP32 for the others.
+ *  FP64 : 8 bytes per value.
+ *  FP32 : 4 bytes per value.
+ *  HILO : bfloat16 pair (hi, lo) with value = hi + lo, packed in 4 bytes.
+ *  S16  : IEEE binary16 of a power-of-two scaled value (2^10 for the density
+ *         deviation, 2^6 for the velocity), stored with stochastic rounding
+ *         driven by a counter-based hash of (seed, step, node, field);
+ *         2 bytes per value. */
+enum { MACLAB_FP64 = 0, MACLAB_FP32 = 1, MACLAB_HILO = 2, MACLAB_S16 = 3 };
+
+/* Faces and boundary kinds. A fixed face holds its physical (rho_b, u_b) on
+ * every node of the face ("physical variables can directly be retained as
+ * the boundary conditions", abstract (i); recipe step (iv)). Both faces of
+ * an axis must be of the same kind. A node on several fixed faces takes the
+ * values of the lowest-numbered face (XLO < XHI < YLO < YHI < ZLO < ZHI), so
+ * side walls own the edges and corners of a lid on the highest face. */
+enum { MACLAB_XLO = 0, MACLAB_XHI, MACLAB_YLO, MACLAB_YHI, MACLAB_ZLO, MACLAB_ZHI };
+enum { MACLAB_BC_PERIODIC = 0, MACLAB_BC_FIXED = 1 };
+
+typedef struct maclab_s* maclab_t;
+
+typedef struct {
+  int32_t lattice;        /* MACLAB_D2Q9 or MACLAB_D3Q19 */
+  int32_t precision;      /* MACLAB_FP64 / FP32 / HILO / S16 */
+  int64_t n[3];           /* node counts including boundary nodes; n[2] = 1 for D2Q9 */
+  double dx;              /* lattice size [m] (> 0) */
+  double nu;              /* kinematic viscosity [m^2/s] (> 0) */
+  double body_force[3];   /* uniform body force per unit volume G = -grad p [N/m^3] */
+  double rho_ref;         /* reference density of the stored deviation (e.g. 1.0) */
+  uint64_t seed;          /* stochastic-rounding stream (S16 only) */
+  void* stream;           /* hipStream_t the library enqueues on; NULL = default stream */
+  void* workspace;        /* caller-owned device memory, 256-byte aligned */
+  size_t workspace_bytes; /* >= maclab_workspace_bytes(cfg) */
+} maclab_config;
+
+/* Bytes of workspace the configuration needs (two state buffers, reduction
+ * partials, a host-transfer staging area). Pure host arithmetic; returns 0
+ * for an invalid configuration. */
+size_t maclab_workspace_bytes(const maclab_config* cfg);
+
+/* Validates cfg, derives e = 6 nu / dx (Eq. (6)) and dt = dx / e, and binds
+ * the workspace. All faces start periodic and the state starts at rest
+ * (rho = rho_ref, u = 0). Invalid configurations return MACLAB_EINVAL (or
+ * MACLAB_EWORKSPACE / MACLAB_EUNSUPPORTED) before any HIP call. */
+int maclab_init(const maclab_config* cfg, maclab_t* out);
+
+/* Sets face `face` to `kind`. For MACLAB_BC_FIXED the face holds density
+ * rho_b and velocity u_b[0..d-1] (physical units); the values are written
+ * into the state at once and are never updated by maclab_step. */
+int maclab_set_bc(maclab_t h, int face, int kind, double rho_b, const double* u_b);
+
+/* Loads physical rho (N values) and u (d*N values) into the state, then
+ * re-imposes the fixed-face values. on_device = 1: device pointers;
+ * on_device = 0: host pointers (copied through the staging area; syncs). */
+int maclab_set_fields(maclab_t h, const double* rho, const double* u, int on_device);
+
+/* Enqueues n time steps (Eqs. (4)-(5) plus the body force of test 2: the
+ * new lattice velocity is (sum_a c_a f_eq_a + dt G / e) / rho'). Asynchronous.
+ * Returns MACLAB_EINVAL if the face kinds of an axis differ. */
+int maclab_step(maclab_t h, int64_t n);
+
+/* Like maclab_step, but after every `check_every` steps reduces the state
+ * and stops early with MACLAB_ENONFINITE when a value is non-finite or the
+ * largest |u|/e reaches 1 (the validity condition of the equilibrium: Mach
+ * number much smaller than one). *done receives the steps completed.
+ * Synchronises at every check. */
+int maclab_step_checked(maclab_t h, int64_t n, int64_t check_every, int64_t* done);
+
+/* Writes physical rho (N values) and u (d*N values). on_device = 0 means
+ * host destinations and synchronises. */
+int maclab_get_fields(maclab_t h, double* rho, double* u, int on_device);
+
+/* FP64 reductions over all nodes, written to host out[7]: mass sum rho,
+ * momentum sum rho u (x, y, z), kinetic energy 1/2 sum rho |u|^2, max |u|/e,
+ * number of nodes holding a non-finite value (excluded from the sums).
+ * Deterministic (fixed reduction order). Synchronises. */
+int maclab_diagnostics(maclab_t h, double out[7]);
+
+/* Host out[6]: particle speed e, time step dt, lattice Reynolds number
+ * R_le = max_fixed |u_b| dx / nu (main text, stability remark after
+ * Eq. (6)), Mach number R_le / 6, steps taken, simulated time steps * dt. */
+int maclab_params(maclab_t h, double out[6]);
+
+/* Native state: the d+1 stored planes of the current step in storage format,
+ * maclab_state_bytes(h) bytes. save copies it to caller device memory; load
+ * restores it bitwise into both ping-pong buffers (including 16-bit
+ * storage), so a run resumed from a saved state repeats the original bit for
+ * bit (for S16 the rounding stream is keyed by the step counter, which load
+ * leaves unchanged). Stream-ordered, asynchronous. */
+size_t maclab_state_bytes(maclab_t h);
+int maclab_save_state(maclab_t h, void* dst_device);
+int maclab_load_state(maclab_t h, const void* src_device);
+
+/* Releases the handle (not the caller's memory). NULL is ignored. */
+void maclab_destroy(maclab_t h);
+
+const char* maclab_last_error(maclab_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MACLAB_H */

@@ -13,6 +13,7 @@ Every function mirrors one step of the paper (Zhou, arXiv:1901.02716):
   dt = dx/e.
 * :func:`run` -- repeated application of Eqs. (4)-(5) [mlb-p.1, mlb-u.1] with
   fixed (Dirichlet) and periodic faces and the body-force term of test 2.
+* :func:`step_at` -- the same step evaluated at sampled nodes only.
 * :func:`diagnostics` -- mass, momentum, kinetic energy, max |u|/e and the
   non-finite count (the conserved moments of Methods, Eqs. (14)-(15)).
 * :func:`adjoint_run` -- reverse-mode derivative of :func:`run` for a
@@ -90,6 +91,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
         lib.oracle_impose_boundary.argtypes = [ctypes.POINTER(_Problem), _dp, _dp]
         lib.oracle_run.argtypes = [ctypes.POINTER(_Problem), _dp, _dp, ctypes.c_int64]
         lib.oracle_diagnostics.argtypes = [ctypes.POINTER(_Problem), _dp, _dp, _dp]
+        lib.oracle_step_at.argtypes = [ctypes.POINTER(_Problem), _dp, _dp, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.c_int64, _dp, _dp]
         if hasattr(lib, "oracle_adjoint_run"):
             lib.oracle_adjoint_run.argtypes = [ctypes.POINTER(_Problem), _dp, _dp, ctypes.c_int64,
                                                _dp, _dp, _dp, _dp]
@@ -192,6 +195,24 @@ def run(p: Problem, rho0: np.ndarray, u0: np.ndarray, steps: int, lib: str | Non
     if rc != 0:
         raise ValueError(f"oracle_run failed ({rc})")
     return rho, u
+
+
+def step_at(p: Problem, rho: np.ndarray, u: np.ndarray, nodes) -> tuple[np.ndarray, np.ndarray]:
+    """One step from (rho, u) evaluated only at the flat node indices `nodes`.
+
+    Returns (rho_new[count], u_new[d, count]). The arrays must already hold
+    the boundary values.
+    """
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    idx = np.ascontiguousarray(np.asarray(nodes, dtype=np.int64).ravel())
+    ro = np.zeros(idx.size)
+    uo = np.zeros((p.d, idx.size))
+    rc = load().oracle_step_at(ctypes.byref(p._c()), _ptr(rho), _ptr(u),
+                               idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), idx.size, _ptr(ro), _ptr(uo))
+    if rc != 0:
+        raise ValueError("invalid problem or node index")
+    return ro, uo
 
 
 def diagnostics(p: Problem, rho: np.ndarray, u: np.ndarray) -> np.ndarray:

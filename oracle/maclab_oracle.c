@@ -180,12 +180,42 @@ int oracle_impose_boundary(const oracle_problem* p, double* rho, double* u) {
   return 0;
 }
 
+/* Eqs. (4)-(5) at one non-fixed node (i, j, k): gathers the equilibria of
+ * the upstream nodes and returns the new density and velocity. */
+static void update_node(const oracle_problem* p, double e, double dt,
+                        const double* rho, const double* u, int64_t i,
+                        int64_t j, int64_t k, double* rho_out,
+                        double* u_out) {
+  const int q = p->q, d = lattice_dims(q);
+  const int(*c)[3] = lattice_c(q);
+  const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
+  const int64_t N = nx * ny * nz;
+  double r = 0.0;
+  double m[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < q; ++a) {
+    /* Source node x - e_a dt = x - c_a. */
+    int64_t si = wrap(i - c[a][0], nx);
+    int64_t sj = wrap(j - c[a][1], ny);
+    int64_t sk = wrap(k - c[a][2], nz);
+    int64_t s = si + nx * (sj + ny * sk);
+    double us[3] = {0.0, 0.0, 0.0};
+    for (int cc = 0; cc < d; ++cc) us[cc] = u[cc * N + s];
+    double f = oracle_feq(q, a, rho[s], us, e);
+    r += f;                                     /* Eq. (4) */
+    for (int cc = 0; cc < d; ++cc) m[cc] += e * (double)c[a][cc] * f;
+  }
+  *rho_out = r;
+  for (int cc = 0; cc < d; ++cc) {
+    /* Eq. (5) plus the body-force term of test 2 (sign per G). */
+    u_out[cc] = m[cc] / r + dt * p->G[cc] / r;
+  }
+}
+
 /* One MacLAB step from (rho, u) into (rho_new, u_new). */
 static void step_once(const oracle_problem* p, double e, double dt,
                       const double* rho, const double* u, double* rho_new,
                       double* u_new) {
-  const int q = p->q, d = lattice_dims(q);
-  const int(*c)[3] = lattice_c(q);
+  const int d = lattice_dims(p->q);
   const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
   const int64_t N = nx * ny * nz;
   for (int64_t k = 0; k < nz; ++k)
@@ -198,26 +228,38 @@ static void step_once(const oracle_problem* p, double e, double dt,
           for (int cc = 0; cc < d; ++cc) u_new[cc * N + x] = u[cc * N + x];
           continue;
         }
-        double r = 0.0;
-        double m[3] = {0.0, 0.0, 0.0};
-        for (int a = 0; a < q; ++a) {
-          /* Source node x - e_a dt = x - c_a. */
-          int64_t si = wrap(i - c[a][0], nx);
-          int64_t sj = wrap(j - c[a][1], ny);
-          int64_t sk = wrap(k - c[a][2], nz);
-          int64_t s = si + nx * (sj + ny * sk);
-          double us[3] = {0.0, 0.0, 0.0};
-          for (int cc = 0; cc < d; ++cc) us[cc] = u[cc * N + s];
-          double f = oracle_feq(q, a, rho[s], us, e);
-          r += f;                                     /* Eq. (4) */
-          for (int cc = 0; cc < d; ++cc) m[cc] += e * (double)c[a][cc] * f;
-        }
-        rho_new[x] = r;
-        for (int cc = 0; cc < d; ++cc) {
-          /* Eq. (5) plus the body-force term of test 2 (sign per G). */
-          u_new[cc * N + x] = m[cc] / r + dt * p->G[cc] / r;
-        }
+        double un[3];
+        update_node(p, e, dt, rho, u, i, j, k, &rho_new[x], un);
+        for (int cc = 0; cc < d; ++cc) u_new[cc * N + x] = un[cc];
       }
+}
+
+/* One step evaluated only at the listed nodes (flat indices): rho_out[s] and
+ * u_out[c * count + s] receive the values after the step. Fixed nodes keep
+ * their values. For checking large lattices on a sample of nodes. */
+int oracle_step_at(const oracle_problem* p, const double* rho,
+                   const double* u, const int64_t* nodes, int64_t count,
+                   double* rho_out, double* u_out) {
+  if (validate(p) || count < 0) return -1;
+  const int d = lattice_dims(p->q);
+  const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
+  const int64_t N = nx * ny * nz;
+  const double e = oracle_particle_speed(p->nu, p->dx);
+  const double dt = p->dx / e;
+  for (int64_t s = 0; s < count; ++s) {
+    const int64_t x = nodes[s];
+    if (x < 0 || x >= N) return -1;
+    const int64_t i = x % nx, j = (x / nx) % ny, k = x / (nx * ny);
+    double un[3] = {0.0, 0.0, 0.0};
+    if (fixed_face(p, i, j, k) >= 0) {
+      rho_out[s] = rho[x];
+      for (int cc = 0; cc < d; ++cc) un[cc] = u[cc * N + x];
+    } else {
+      update_node(p, e, dt, rho, u, i, j, k, &rho_out[s], un);
+    }
+    for (int cc = 0; cc < d; ++cc) u_out[cc * count + s] = un[cc];
+  }
+  return 0;
 }
 
 /* Advances (rho, u) in place by `steps` time steps. rho has N = nx*ny*nz

@@ -1,0 +1,141 @@
+// Device-side building blocks of the MacLAB step for gfx950: lattice tables,
+// the per-step parameter block, storage codecs and the stochastic-rounding
+// hash. Everything here is GPU code of this library; it shares nothing with
+// the CPU oracle used by the tests.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace maclab {
+
+// ---------------------------------------------------------------- lattices
+// Unit velocities c_a = e_a / e and weights. D2Q9 in the order listed with
+// Eq. (1) of the paper, weights 4/9, 1/9, 1/36 (with Eq. (2)); D3Q19 in the
+// order listed at the start of the numerical tests, weights 1/3, 1/18, 1/36.
+template <int Q>
+struct Lattice;
+
+template <>
+struct Lattice<9> {
+  static constexpr int D = 2;
+  static constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  static constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  static constexpr int wnum[9] = {16, 4, 4, 4, 4, 1, 1, 1, 1};  // w = wnum / 36
+};
+
+template <>
+struct Lattice<19> {
+  static constexpr int D = 3;
+  static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, -1, 1};
+  static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1, 0, 0, 0, 0};
+  static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+  static constexpr int wnum[19] = {12, 2, 2, 2, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
+};
+
+// ------------------------------------------------------------- parameters
+// Everything a step kernel needs, passed by value. Lattice units: the stored
+// velocity is u~ = u / e and g = dt G / e is the per-step velocity increment
+// of the body force (test 2 of the paper, with G = -dp/dx).
+struct StepParams {
+  int64_t nx, ny, nz;   // node counts
+  int64_t plane;        // elements between consecutive planes of one buffer
+  int fixed[3];         // 1 if both faces of the axis are fixed (Dirichlet)
+  double rho_ref;       // density the stored deviation refers to
+  double g[3];          // dt * G / e
+  uint64_t seed;        // S16 stochastic rounding
+  uint64_t step;        // index of the step being computed (S16 rounding key)
+};
+
+// --------------------------------------------------------- storage codecs
+// A codec maps the compute type T to the stored element and back. Field index
+// 0 is the density deviation rho - rho_ref, fields 1..D are u~.
+__device__ __forceinline__ uint32_t f32_bits(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ float bits_f32(uint32_t b) { return __uint_as_float(b); }
+
+// Round-to-nearest-even float32 -> bfloat16 bits (NaN stays NaN).
+__device__ __forceinline__ uint32_t bf16_rne(float v) {
+  uint32_t b = f32_bits(v);
+  if ((b & 0x7f800000u) == 0x7f800000u) return (b >> 16) | ((b & 0xffffu) ? 0x40u : 0u);
+  return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
+}
+
+struct CodecF64 {
+  using elem = double;
+  using T = double;
+  static constexpr int bytes = 8;
+  __device__ static T dec(elem s, int) { return s; }
+  __device__ static elem enc(T v, int, uint32_t) { return v; }
+};
+
+struct CodecF32 {
+  using elem = float;
+  using T = float;
+  static constexpr int bytes = 4;
+  __device__ static T dec(elem s, int) { return s; }
+  __device__ static elem enc(T v, int, uint32_t) { return v; }
+};
+
+// Split bfloat16: hi = bf16(v), lo = bf16(v - hi), packed as (hi << 16) | lo.
+struct CodecHILO {
+  using elem = uint32_t;
+  using T = float;
+  static constexpr int bytes = 4;
+  __device__ static T dec(elem s, int) {
+    return bits_f32(s & 0xffff0000u) + bits_f32(s << 16);
+  }
+  __device__ static elem enc(T v, int, uint32_t) {
+    uint32_t hi = bf16_rne(v);
+    float rest = v - bits_f32(hi << 16);
+    return (hi << 16) | bf16_rne(rest);
+  }
+};
+
+// Scaled binary16 with stochastic rounding: the value times 2^10 (density
+// deviation) or 2^6 (velocity) is rounded to one of its two neighbouring
+// binary16 values with probability proportional to proximity. `rnd` supplies
+// 13 uniform bits: they are added below the 10-bit binary16 mantissa of the
+// float32 value, which is then truncated, so the conversion is exact for
+// results in the binary16 normal range (smaller magnitudes round to nearest).
+struct CodecS16 {
+  using elem = uint16_t;
+  using T = float;
+  static constexpr int bytes = 2;
+  __device__ static float scale(int field) { return field == 0 ? 1024.0f : 64.0f; }
+  __device__ static float inv_scale(int field) { return field == 0 ? (1.0f / 1024.0f) : (1.0f / 64.0f); }
+  __device__ static T dec(elem s, int field) {
+    _Float16 h = __builtin_bit_cast(_Float16, s);
+    return (float)h * inv_scale(field);
+  }
+  __device__ static elem enc(T v, int field, uint32_t rnd) {
+    float x = v * scale(field);
+    uint32_t b = f32_bits(x);
+    if ((b & 0x7f800000u) != 0x7f800000u) b = (b + (rnd & 0x1fffu)) & ~0x1fffu;
+    _Float16 h = (_Float16)bits_f32(b);
+    return __builtin_bit_cast(uint16_t, h);
+  }
+};
+
+// Counter-based hash (a 32-bit integer finaliser applied to a combination of
+// seed, step, node and field) giving the rounding bits of CodecS16.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t sr_bits(uint64_t seed, uint64_t step, int64_t node, int field) {
+  uint32_t h = mix32((uint32_t)seed ^ mix32((uint32_t)(seed >> 32) + (uint32_t)step * 0x9e3779b9u));
+  return mix32(h ^ mix32((uint32_t)node * 4u + (uint32_t)field + (uint32_t)(node >> 30)));
+}
+
+template <class C>
+struct needs_rng { static constexpr bool value = false; };
+template <>
+struct needs_rng<CodecS16> { static constexpr bool value = true; };
+
+}  // namespace maclab

@@ -1,0 +1,54 @@
+// Host-side declarations shared by the library's translation units: the
+// handle, and the launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/maclab.h"
+#include "device.h"
+
+namespace maclab {
+
+// Values of the six faces as the kernels see them (physical units except
+// where noted).
+struct FaceValues {
+  int kind[6];
+  double rho[6];
+  double u[6][3];
+};
+
+struct Layout {
+  int q = 0, d = 0, precision = 0, bytes = 0;
+  int64_t nx = 0, ny = 0, nz = 0, N = 0;
+  int64_t plane = 0;          // elements per plane (N rounded up)
+  size_t state_bytes = 0;     // (d + 1) planes
+  size_t partial_bytes = 0;   // reduction partials
+  size_t staging_bytes = 0;   // host transfer staging
+  size_t workspace_bytes = 0;
+};
+
+constexpr int kDiagBlocks = 1024;  // partial sums of the diagnostics reduction
+constexpr int kDiagValues = 8;     // M, Px, Py, Pz, E, max|u~|, non-finite, pad
+
+// Launchers (kernels_generic.hip). All enqueue on `s` and return the launch
+// status.
+hipError_t launch_step_generic(const Layout& L, const void* src, void* dst, const StepParams& p,
+                               hipStream_t s);
+hipError_t launch_impose_bc(const Layout& L, void* buf0, void* buf1, const FaceValues& fv, double rho_ref,
+                            double e, hipStream_t s);
+hipError_t launch_encode(const Layout& L, void* plane_dst, const double* src, int64_t count, double offset,
+                         double mul, int field, hipStream_t s);
+hipError_t launch_decode(const Layout& L, double* dst, const void* plane_src, int64_t count, double offset,
+                         double mul, int field, hipStream_t s);
+hipError_t launch_diagnostics(const Layout& L, const void* state, double rho_ref, double e, double* partials,
+                              double* result, hipStream_t s);
+
+// Fast paths (kernels_fast.hip). `supported` tells whether a fast kernel
+// handles the layout and boundary kinds; launch enqueues one step.
+bool fast_step_supported(const Layout& L, const StepParams& p);
+hipError_t launch_step_fast(const Layout& L, const void* src, void* dst, const StepParams& p, hipStream_t s);
+
+}  // namespace maclab

@@ -1,0 +1,284 @@
+// General-shape kernels of the MacLAB library for gfx950: the step for any
+// node counts and boundary kinds, the field codecs, boundary imposition and
+// the FP64 diagnostics reduction.
+//
+// The step is the gather of the paper's Eqs. (4)-(5): the new density and
+// momentum of node x are the sums over links a of the equilibrium f_eq_a
+// (Eq. (2)) evaluated at the upstream node x - c_a. It is computed in
+// deviation form: with rho = rho_ref + drho and phi_a the bracket of Eq. (2),
+//   F^_a = f_eq_a - w_a rho_ref = w_a [drho + rho (phi_a - 1)],
+// and because sum_a w_a = 1 and sum_a w_a c_a = 0,
+//   drho' = sum_a F^_a(x - c_a),   m' = sum_a c_a F^_a(x - c_a),
+// which is Eqs. (4)-(5) exactly while only small numbers are summed.
+// The new lattice velocity is u~' = (m' + g) / (rho_ref + drho').
+#include "internal.h"
+
+namespace maclab {
+
+template <class C>
+__device__ __forceinline__ typename C::T load_field(const typename C::elem* base, int64_t plane, int f,
+                                                    int64_t node) {
+  return C::dec(base[f * plane + node], f);
+}
+
+template <class C>
+__device__ __forceinline__ void store_field(typename C::elem* base, int64_t plane, int f, int64_t node,
+                                            typename C::T v, const StepParams& p) {
+  uint32_t r = 0;
+  if constexpr (needs_rng<C>::value) r = sr_bits(p.seed, p.step, node, f);
+  base[f * plane + node] = C::enc(v, f, r);
+}
+
+__device__ __forceinline__ int64_t wrap_idx(int64_t v, int64_t n) {
+  return v < 0 ? v + n : (v >= n ? v - n : v);
+}
+
+// One thread per destination node; the upstream values come through the
+// cache. Handles every shape, periodic wrap on any axis and fixed faces.
+template <int Q, class C>
+__global__ __launch_bounds__(256) void step_generic_kernel(const typename C::elem* __restrict__ src,
+                                                           typename C::elem* __restrict__ dst,
+                                                           StepParams p) {
+  using Lat = Lattice<Q>;
+  using T = typename C::T;
+  constexpr int D = Lat::D;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = (int64_t)blockIdx.y * blockDim.y + threadIdx.y;
+  const int64_t k = blockIdx.z;
+  if (i >= p.nx || j >= p.ny) return;
+  if ((p.fixed[0] && (i == 0 || i == p.nx - 1)) || (p.fixed[1] && (j == 0 || j == p.ny - 1)) ||
+      (p.fixed[2] && (k == 0 || k == p.nz - 1)))
+    return;  // fixed nodes hold their values in both buffers
+  const T rho_ref = (T)p.rho_ref;
+  T drho = 0, mx = 0, my = 0, mz = 0;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const int cx = Lat::cx[a], cy = Lat::cy[a], cz = Lat::cz[a];
+    const int64_t si = wrap_idx(i - cx, p.nx);
+    const int64_t sj = wrap_idx(j - cy, p.ny);
+    const int64_t sk = wrap_idx(k - cz, p.nz);
+    const int64_t s = si + p.nx * (sj + p.ny * sk);
+    const T dr = load_field<C>(src, p.plane, 0, s);
+    const T ux = load_field<C>(src, p.plane, 1, s);
+    const T uy = load_field<C>(src, p.plane, 2, s);
+    T uz = 0;
+    if constexpr (D == 3) uz = load_field<C>(src, p.plane, 3, s);
+    const T rho = rho_ref + dr;
+    const T cu = (T)cx * ux + (T)cy * uy + (T)cz * uz;
+    const T uu = ux * ux + uy * uy + uz * uz;
+    const T w = (T)Lat::wnum[a] / (T)36;
+    const T F = w * (dr + rho * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu));
+    drho += F;
+    if (cx) mx += (T)cx * F;
+    if (cy) my += (T)cy * F;
+    if (cz) mz += (T)cz * F;
+  }
+  const T inv = (T)1 / (rho_ref + drho);
+  const int64_t x = i + p.nx * (j + p.ny * k);
+  store_field<C>(dst, p.plane, 0, x, drho, p);
+  store_field<C>(dst, p.plane, 1, x, (mx + (T)p.g[0]) * inv, p);
+  store_field<C>(dst, p.plane, 2, x, (my + (T)p.g[1]) * inv, p);
+  if constexpr (D == 3) store_field<C>(dst, p.plane, 3, x, (mz + (T)p.g[2]) * inv, p);
+}
+
+// Writes the fixed-face values into both buffers; a node on several fixed
+// faces takes the values of the lowest-numbered one.
+template <class C>
+__global__ void impose_bc_kernel(typename C::elem* b0, typename C::elem* b1, int64_t nx, int64_t ny,
+                                 int64_t nz, int64_t plane, int d, FaceValues fv, double rho_ref, double e) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nx * ny * nz) return;
+  const int64_t idx[3] = {x % nx, (x / nx) % ny, x / (nx * ny)};
+  const int64_t n[3] = {nx, ny, nz};
+  int face = -1;
+  for (int f = 0; f < 6 && face < 0; ++f) {
+    if (fv.kind[f] != MACLAB_BC_FIXED) continue;
+    const int ax = f / 2;
+    if (idx[ax] == ((f & 1) ? n[ax] - 1 : 0)) face = f;
+  }
+  if (face < 0) return;
+  typename C::elem v[4];
+  v[0] = C::enc((typename C::T)(fv.rho[face] - rho_ref), 0, 0x1000u);
+  for (int c = 0; c < d; ++c) v[1 + c] = C::enc((typename C::T)(fv.u[face][c] / e), 1 + c, 0x1000u);
+  for (int f = 0; f <= d; ++f) {
+    b0[f * plane + x] = v[f];
+    b1[f * plane + x] = v[f];
+  }
+}
+
+// Physical float64 -> stored: value = (src - offset) * mul, rounded to nearest.
+template <class C>
+__global__ void encode_kernel(typename C::elem* dst, const double* __restrict__ src, int64_t count,
+                              double offset, double mul, int field) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  dst[i] = C::enc((typename C::T)((src[i] - offset) * mul), field, 0x1000u);
+}
+
+// Stored -> physical float64: dst = offset + mul * value.
+template <class C>
+__global__ void decode_kernel(double* dst, const typename C::elem* __restrict__ src, int64_t count,
+                              double offset, double mul, int field) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  dst[i] = offset + mul * (double)C::dec(src[i], field);
+}
+
+// ------------------------------------------------------------ diagnostics
+// Mass, momentum and kinetic energy in FP64 (the conserved moments of the
+// equilibrium, Methods, Eqs. (14)-(15)), max |u~| and the non-finite count.
+// Each block reduces its grid-stride share with 64-lane wavefront shuffles,
+// then across waves through LDS, and writes one partial row; a single block
+// then folds the rows in a fixed order, so the result is deterministic.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  return v;
+}
+
+template <class C>
+__global__ __launch_bounds__(256) void diag_partial_kernel(const typename C::elem* __restrict__ s,
+                                                           int64_t N, int64_t plane, int d, double rho_ref,
+                                                           double e, double* __restrict__ partials) {
+  double acc[kDiagValues] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const double rho = rho_ref + (double)C::dec(s[x], 0);
+    double ut[3] = {0, 0, 0};
+    bool finite = isfinite(rho);
+    for (int c = 0; c < d; ++c) {
+      ut[c] = (double)C::dec(s[(1 + c) * plane + x], 1 + c);
+      finite = finite && isfinite(ut[c]);
+    }
+    if (!finite) {
+      acc[6] += 1.0;
+      continue;
+    }
+    const double uu = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+    acc[0] += rho;
+    for (int c = 0; c < 3; ++c) acc[1 + c] += rho * e * ut[c];
+    acc[4] += 0.5 * rho * e * e * uu;
+    acc[5] = fmax(acc[5], sqrt(uu));
+  }
+  __shared__ double red[kDiagValues][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < kDiagValues; ++v) {
+    const double r = (v == 5) ? wave_max(acc[v]) : wave_sum(acc[v]);
+    if (lane == 0) red[v][wave] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < kDiagValues) {
+    const int v = threadIdx.x;
+    double r = red[v][0];
+    for (int w = 1; w < 4; ++w) r = (v == 5) ? fmax(r, red[v][w]) : r + red[v][w];
+    partials[(int64_t)blockIdx.x * kDiagValues + v] = r;
+  }
+}
+
+__global__ __launch_bounds__(256) void diag_final_kernel(const double* __restrict__ partials, int nblocks,
+                                                         double* __restrict__ out) {
+  __shared__ double red[kDiagValues][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int v = 0; v < kDiagValues; ++v) {
+    double acc = 0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+      const double x = partials[(int64_t)b * kDiagValues + v];
+      acc = (v == 5) ? fmax(acc, x) : acc + x;
+    }
+    const double r = (v == 5) ? wave_max(acc) : wave_sum(acc);
+    if (lane == 0) red[v][wave] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < kDiagValues) {
+    const int v = threadIdx.x;
+    double r = red[v][0];
+    for (int w = 1; w < 4; ++w) r = (v == 5) ? fmax(r, red[v][w]) : r + red[v][w];
+    out[v] = r;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+template <class F>
+static hipError_t dispatch_codec(int precision, F&& f) {
+  switch (precision) {
+    case MACLAB_FP64: return f(CodecF64{});
+    case MACLAB_FP32: return f(CodecF32{});
+    case MACLAB_HILO: return f(CodecHILO{});
+    case MACLAB_S16: return f(CodecS16{});
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_step_generic(const Layout& L, const void* src, void* dst, const StepParams& p,
+                               hipStream_t s) {
+  const dim3 block(64, 4, 1);
+  const dim3 grid((unsigned)((L.nx + 63) / 64), (unsigned)((L.ny + 3) / 4), (unsigned)L.nz);
+  return dispatch_codec(L.precision, [&](auto codec) {
+    using C = decltype(codec);
+    using E = typename C::elem;
+    if (L.q == 9)
+      hipLaunchKernelGGL((step_generic_kernel<9, C>), grid, block, 0, s, (const E*)src, (E*)dst, p);
+    else
+      hipLaunchKernelGGL((step_generic_kernel<19, C>), grid, block, 0, s, (const E*)src, (E*)dst, p);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_impose_bc(const Layout& L, void* b0, void* b1, const FaceValues& fv, double rho_ref,
+                            double e, hipStream_t s) {
+  const unsigned blocks = (unsigned)((L.N + 255) / 256);
+  return dispatch_codec(L.precision, [&](auto codec) {
+    using C = decltype(codec);
+    using E = typename C::elem;
+    hipLaunchKernelGGL((impose_bc_kernel<C>), dim3(blocks), dim3(256), 0, s, (E*)b0, (E*)b1, L.nx, L.ny,
+                       L.nz, L.plane, L.d, fv, rho_ref, e);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_encode(const Layout& L, void* dst, const double* src, int64_t count, double offset,
+                         double mul, int field, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((count + 255) / 256);
+  return dispatch_codec(L.precision, [&](auto codec) {
+    using C = decltype(codec);
+    hipLaunchKernelGGL((encode_kernel<C>), dim3(blocks), dim3(256), 0, s, (typename C::elem*)dst, src,
+                       count, offset, mul, field);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_decode(const Layout& L, double* dst, const void* src, int64_t count, double offset,
+                         double mul, int field, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((count + 255) / 256);
+  return dispatch_codec(L.precision, [&](auto codec) {
+    using C = decltype(codec);
+    hipLaunchKernelGGL((decode_kernel<C>), dim3(blocks), dim3(256), 0, s, dst,
+                       (const typename C::elem*)src, count, offset, mul, field);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_diagnostics(const Layout& L, const void* state, double rho_ref, double e, double* partials,
+                              double* result, hipStream_t s) {
+  const int64_t want = (L.N + 255) / 256;
+  const int blocks = (int)(want < kDiagBlocks ? (want > 0 ? want : 1) : kDiagBlocks);
+  hipError_t err = dispatch_codec(L.precision, [&](auto codec) {
+    using C = decltype(codec);
+    hipLaunchKernelGGL((diag_partial_kernel<C>), dim3(blocks), dim3(256), 0, s,
+                       (const typename C::elem*)state, L.N, L.plane, L.d, rho_ref, e, partials);
+    return hipGetLastError();
+  });
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, partials, blocks, result);
+  return hipGetLastError();
+}
+
+}  // namespace maclab

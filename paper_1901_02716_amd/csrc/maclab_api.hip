@@ -1,0 +1,371 @@
+// C ABI of the MacLAB library (include/maclab.h): validation, workspace
+// layout, parameter map, boundary bookkeeping and launch sequencing.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+
+#include "internal.h"
+
+using namespace maclab;
+
+struct maclab_s {
+  maclab_config cfg;
+  Layout L;
+  hipStream_t stream = nullptr;
+  char* state[2] = {nullptr, nullptr};
+  int cur = 0;
+  double* partials = nullptr;
+  double* result = nullptr;  // kDiagValues doubles after the partials
+  char* staging = nullptr;
+  FaceValues fv;
+  double e = 0, dt = 0;
+  int64_t steps = 0;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+constexpr size_t kAlign = 256;
+constexpr size_t kStagingMax = size_t(8) << 20;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int fail(maclab_t h, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(maclab_t h, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (h)
+    h->err = buf;
+  else
+    g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(h, expr)                                                                              \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess) return fail((h), MACLAB_EHIP, "%s: %s", #expr, hipGetErrorString(e_));      \
+  } while (0)
+
+// Validates the configuration and fills the layout. Pure host arithmetic.
+int make_layout(const maclab_config* c, Layout* L, std::string* why) {
+  if (!c) {
+    *why = "config is NULL";
+    return MACLAB_EINVAL;
+  }
+  if (c->lattice != MACLAB_D2Q9 && c->lattice != MACLAB_D3Q19) {
+    *why = "lattice must be MACLAB_D2Q9 (9) or MACLAB_D3Q19 (19)";
+    return MACLAB_EUNSUPPORTED;
+  }
+  if (c->precision < MACLAB_FP64 || c->precision > MACLAB_S16) {
+    *why = "precision must be FP64, FP32, HILO or S16";
+    return MACLAB_EUNSUPPORTED;
+  }
+  if (!(c->dx > 0) || !isfinite(c->dx) || !(c->nu > 0) || !isfinite(c->nu)) {
+    *why = "dx and nu must be finite and positive";
+    return MACLAB_EINVAL;
+  }
+  if (!(c->rho_ref > 0) || !isfinite(c->rho_ref)) {
+    *why = "rho_ref must be finite and positive";
+    return MACLAB_EINVAL;
+  }
+  for (int i = 0; i < 3; ++i)
+    if (!isfinite(c->body_force[i])) {
+      *why = "body_force must be finite";
+      return MACLAB_EINVAL;
+    }
+  const int d = c->lattice == MACLAB_D2Q9 ? 2 : 3;
+  for (int i = 0; i < 3; ++i)
+    if (c->n[i] < 1 || c->n[i] > (int64_t(1) << 24)) {
+      *why = "node counts must be in [1, 2^24]";
+      return MACLAB_EINVAL;
+    }
+  if (d == 2 && c->n[2] != 1) {
+    *why = "D2Q9 needs n[2] == 1";
+    return MACLAB_EINVAL;
+  }
+  const int64_t N = c->n[0] * c->n[1] * c->n[2];
+  if (N > (int64_t(1) << 34)) {
+    *why = "lattice too large";
+    return MACLAB_EINVAL;
+  }
+  L->q = c->lattice;
+  L->d = d;
+  L->precision = c->precision;
+  L->bytes = c->precision == MACLAB_FP64 ? 8 : (c->precision == MACLAB_S16 ? 2 : 4);
+  L->nx = c->n[0];
+  L->ny = c->n[1];
+  L->nz = c->n[2];
+  L->N = N;
+  L->plane = (int64_t)round_up((size_t)N, 512);
+  L->state_bytes = (size_t)(d + 1) * (size_t)L->plane * (size_t)L->bytes;
+  L->partial_bytes = round_up(sizeof(double) * (kDiagBlocks + 1) * kDiagValues, kAlign);
+  L->staging_bytes = std::min(kStagingMax, round_up(sizeof(double) * (size_t)N, kAlign));
+  L->workspace_bytes = 2 * round_up(L->state_bytes, kAlign) + L->partial_bytes + L->staging_bytes;
+  return MACLAB_OK;
+}
+
+StepParams make_params(const maclab_t h) {
+  StepParams p;
+  p.nx = h->L.nx;
+  p.ny = h->L.ny;
+  p.nz = h->L.nz;
+  p.plane = h->L.plane;
+  for (int ax = 0; ax < 3; ++ax) p.fixed[ax] = h->fv.kind[2 * ax] == MACLAB_BC_FIXED;
+  p.rho_ref = h->cfg.rho_ref;
+  for (int i = 0; i < 3; ++i) p.g[i] = (i < h->L.d) ? h->dt * h->cfg.body_force[i] / h->e : 0.0;
+  p.seed = h->cfg.seed;
+  p.step = (uint64_t)h->steps;
+  return p;
+}
+
+int check_faces(maclab_t h) {
+  for (int ax = 0; ax < h->L.d; ++ax) {
+    if (h->fv.kind[2 * ax] != h->fv.kind[2 * ax + 1])
+      return fail(h, MACLAB_EINVAL, "faces of axis %d differ (both must be periodic or both fixed)", ax);
+    const int64_t n = ax == 0 ? h->L.nx : (ax == 1 ? h->L.ny : h->L.nz);
+    if (h->fv.kind[2 * ax] == MACLAB_BC_FIXED && n < 3)
+      return fail(h, MACLAB_EINVAL, "fixed faces on axis %d need at least 3 nodes", ax);
+  }
+  return MACLAB_OK;
+}
+
+int impose(maclab_t h) {
+  HIP_TRY(h, launch_impose_bc(h->L, h->state[0], h->state[1], h->fv, h->cfg.rho_ref, h->e, h->stream));
+  return MACLAB_OK;
+}
+
+char* plane_ptr(maclab_t h, int buf, int field) {
+  return h->state[buf] + (size_t)field * (size_t)h->L.plane * (size_t)h->L.bytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t maclab_workspace_bytes(const maclab_config* cfg) {
+  Layout L;
+  std::string why;
+  if (make_layout(cfg, &L, &why) != MACLAB_OK) return 0;
+  return L.workspace_bytes;
+}
+
+int maclab_init(const maclab_config* cfg, maclab_t* out) {
+  if (!out) return fail(nullptr, MACLAB_EINVAL, "out is NULL");
+  *out = nullptr;
+  Layout L;
+  std::string why;
+  int rc = make_layout(cfg, &L, &why);
+  if (rc != MACLAB_OK) return fail(nullptr, rc, "maclab_init: %s", why.c_str());
+  if (!cfg->workspace) return fail(nullptr, MACLAB_EWORKSPACE, "maclab_init: workspace is NULL");
+  if ((uintptr_t)cfg->workspace % kAlign)
+    return fail(nullptr, MACLAB_EWORKSPACE, "maclab_init: workspace must be %zu-byte aligned", kAlign);
+  if (cfg->workspace_bytes < L.workspace_bytes)
+    return fail(nullptr, MACLAB_EWORKSPACE, "maclab_init: workspace has %zu bytes, needs %zu",
+                cfg->workspace_bytes, L.workspace_bytes);
+  maclab_t h = new (std::nothrow) maclab_s();
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "maclab_init: out of host memory");
+  h->cfg = *cfg;
+  h->L = L;
+  h->stream = (hipStream_t)cfg->stream;
+  char* ws = (char*)cfg->workspace;
+  const size_t sb = round_up(L.state_bytes, kAlign);
+  h->state[0] = ws;
+  h->state[1] = ws + sb;
+  h->partials = (double*)(ws + 2 * sb);
+  h->result = h->partials + (size_t)kDiagBlocks * kDiagValues;
+  h->staging = ws + 2 * sb + L.partial_bytes;
+  for (int f = 0; f < 6; ++f) {
+    h->fv.kind[f] = MACLAB_BC_PERIODIC;
+    h->fv.rho[f] = cfg->rho_ref;
+    for (int c = 0; c < 3; ++c) h->fv.u[f][c] = 0.0;
+  }
+  h->e = 6.0 * cfg->nu / cfg->dx;  // Eq. (6)
+  h->dt = cfg->dx / h->e;          // text after Eq. (6)
+  // state at rest: zero deviation and zero velocity in every codec
+  hipError_t e1 = hipMemsetAsync(ws, 0, 2 * sb, h->stream);
+  if (e1 != hipSuccess) {
+    int code = fail(nullptr, MACLAB_EHIP, "maclab_init: hipMemsetAsync: %s", hipGetErrorString(e1));
+    delete h;
+    return code;
+  }
+  *out = h;
+  return MACLAB_OK;
+}
+
+int maclab_set_bc(maclab_t h, int face, int kind, double rho_b, const double* u_b) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (face < 0 || face > 5) return fail(h, MACLAB_EINVAL, "face %d out of range", face);
+  if (face / 2 >= h->L.d) return fail(h, MACLAB_EINVAL, "face %d does not exist in 2D", face);
+  if (kind != MACLAB_BC_PERIODIC && kind != MACLAB_BC_FIXED)
+    return fail(h, MACLAB_EINVAL, "unknown boundary kind %d", kind);
+  if (kind == MACLAB_BC_FIXED) {
+    if (!u_b) return fail(h, MACLAB_EINVAL, "u_b is NULL");
+    if (!(rho_b > 0) || !isfinite(rho_b)) return fail(h, MACLAB_EINVAL, "rho_b must be finite and positive");
+    for (int c = 0; c < h->L.d; ++c)
+      if (!isfinite(u_b[c])) return fail(h, MACLAB_EINVAL, "u_b must be finite");
+  }
+  h->fv.kind[face] = kind;
+  if (kind == MACLAB_BC_FIXED) {
+    h->fv.rho[face] = rho_b;
+    for (int c = 0; c < 3; ++c) h->fv.u[face][c] = c < h->L.d ? u_b[c] : 0.0;
+  }
+  return impose(h);
+}
+
+int maclab_set_fields(maclab_t h, const double* rho, const double* u, int on_device) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!rho || !u) return fail(h, MACLAB_EINVAL, "rho and u must not be NULL");
+  const Layout& L = h->L;
+  const double offsets[4] = {h->cfg.rho_ref, 0, 0, 0};
+  const double muls[4] = {1.0, 1.0 / h->e, 1.0 / h->e, 1.0 / h->e};
+  for (int f = 0; f <= L.d; ++f) {
+    const double* src = f == 0 ? rho : u + (size_t)(f - 1) * (size_t)L.N;
+    if (on_device) {
+      HIP_TRY(h, launch_encode(L, plane_ptr(h, h->cur, f), src, L.N, offsets[f], muls[f], f, h->stream));
+    } else {
+      const int64_t chunk = (int64_t)(L.staging_bytes / sizeof(double));
+      for (int64_t off = 0; off < L.N; off += chunk) {
+        const int64_t cnt = std::min(chunk, L.N - off);
+        HIP_TRY(h, hipMemcpyAsync(h->staging, src + off, sizeof(double) * cnt, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(h, launch_encode(L, plane_ptr(h, h->cur, f) + (size_t)off * L.bytes, (const double*)h->staging,
+                                 cnt, offsets[f], muls[f], f, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));  // staging is reused
+      }
+    }
+  }
+  // the other buffer gets the same state, so fixed nodes agree in both
+  HIP_TRY(h, hipMemcpyAsync(h->state[h->cur ^ 1], h->state[h->cur], L.state_bytes, hipMemcpyDeviceToDevice,
+                            h->stream));
+  return impose(h);
+}
+
+int maclab_step(maclab_t h, int64_t n) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (n < 0) return fail(h, MACLAB_EINVAL, "negative step count");
+  int rc = check_faces(h);
+  if (rc) return rc;
+  StepParams p = make_params(h);
+  const bool fast = fast_step_supported(h->L, p);
+  for (int64_t s = 0; s < n; ++s) {
+    p.step = (uint64_t)h->steps;
+    const void* src = h->state[h->cur];
+    void* dst = h->state[h->cur ^ 1];
+    if (fast)
+      HIP_TRY(h, launch_step_fast(h->L, src, dst, p, h->stream));
+    else
+      HIP_TRY(h, launch_step_generic(h->L, src, dst, p, h->stream));
+    h->cur ^= 1;
+    ++h->steps;
+  }
+  return MACLAB_OK;
+}
+
+int maclab_diagnostics(maclab_t h, double out[7]) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!out) return fail(h, MACLAB_EINVAL, "out is NULL");
+  HIP_TRY(h, launch_diagnostics(h->L, h->state[h->cur], h->cfg.rho_ref, h->e, h->partials, h->result,
+                                h->stream));
+  double r[kDiagValues];
+  HIP_TRY(h, hipMemcpyAsync(r, h->result, sizeof r, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  for (int i = 0; i < 7; ++i) out[i] = r[i];
+  return MACLAB_OK;
+}
+
+int maclab_step_checked(maclab_t h, int64_t n, int64_t check_every, int64_t* done) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (check_every < 1) return fail(h, MACLAB_EINVAL, "check_every must be >= 1");
+  int64_t k = 0;
+  if (done) *done = 0;
+  while (k < n) {
+    const int64_t m = std::min(check_every, n - k);
+    int rc = maclab_step(h, m);
+    if (rc) return rc;
+    k += m;
+    if (done) *done = k;
+    double d[7];
+    rc = maclab_diagnostics(h, d);
+    if (rc) return rc;
+    if (d[6] > 0 || !(d[5] < 1.0))
+      return fail(h, MACLAB_ENONFINITE, "step %lld: %.0f non-finite nodes, max |u|/e = %g", (long long)h->steps,
+                  d[6], d[5]);
+  }
+  return MACLAB_OK;
+}
+
+int maclab_get_fields(maclab_t h, double* rho, double* u, int on_device) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!rho || !u) return fail(h, MACLAB_EINVAL, "rho and u must not be NULL");
+  const Layout& L = h->L;
+  const double offsets[4] = {h->cfg.rho_ref, 0, 0, 0};
+  const double muls[4] = {1.0, h->e, h->e, h->e};
+  for (int f = 0; f <= L.d; ++f) {
+    double* dst = f == 0 ? rho : u + (size_t)(f - 1) * (size_t)L.N;
+    if (on_device) {
+      HIP_TRY(h, launch_decode(L, dst, plane_ptr(h, h->cur, f), L.N, offsets[f], muls[f], f, h->stream));
+    } else {
+      const int64_t chunk = (int64_t)(L.staging_bytes / sizeof(double));
+      for (int64_t off = 0; off < L.N; off += chunk) {
+        const int64_t cnt = std::min(chunk, L.N - off);
+        HIP_TRY(h, launch_decode(L, (double*)h->staging, plane_ptr(h, h->cur, f) + (size_t)off * L.bytes, cnt,
+                                 offsets[f], muls[f], f, h->stream));
+        HIP_TRY(h, hipMemcpyAsync(dst + off, h->staging, sizeof(double) * cnt, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+      }
+    }
+  }
+  return MACLAB_OK;
+}
+
+int maclab_params(maclab_t h, double out[6]) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!out) return fail(h, MACLAB_EINVAL, "out is NULL");
+  double umax = 0;
+  for (int f = 0; f < 2 * h->L.d; ++f) {
+    if (h->fv.kind[f] != MACLAB_BC_FIXED) continue;
+    double s = 0;
+    for (int c = 0; c < h->L.d; ++c) s += h->fv.u[f][c] * h->fv.u[f][c];
+    umax = std::max(umax, sqrt(s));
+  }
+  out[0] = h->e;
+  out[1] = h->dt;
+  out[2] = umax * h->cfg.dx / h->cfg.nu;
+  out[3] = out[2] / 6.0;
+  out[4] = (double)h->steps;
+  out[5] = (double)h->steps * h->dt;
+  return MACLAB_OK;
+}
+
+size_t maclab_state_bytes(maclab_t h) { return h ? h->L.state_bytes : 0; }
+
+int maclab_save_state(maclab_t h, void* dst) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!dst) return fail(h, MACLAB_EINVAL, "dst is NULL");
+  HIP_TRY(h, hipMemcpyAsync(dst, h->state[h->cur], h->L.state_bytes, hipMemcpyDeviceToDevice, h->stream));
+  return MACLAB_OK;
+}
+
+int maclab_load_state(maclab_t h, const void* src) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!src) return fail(h, MACLAB_EINVAL, "src is NULL");
+  HIP_TRY(h, hipMemcpyAsync(h->state[0], src, h->L.state_bytes, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->state[1], src, h->L.state_bytes, hipMemcpyDeviceToDevice, h->stream));
+  return MACLAB_OK;
+}
+
+void maclab_destroy(maclab_t h) { delete h; }
+
+const char* maclab_last_error(maclab_t h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+}  // extern "C"

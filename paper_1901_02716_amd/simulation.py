@@ -1,0 +1,159 @@
+"""Python face of the MacLAB library: one handle per simulation.
+
+PyTorch supplies the device memory (the workspace is a ``torch.uint8``
+tensor) and the HIP stream (the current torch stream of the device); every
+step of the method runs in the library's HIP kernels. There is no CPU path:
+without the built library or a GPU, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_PRECISIONS = {"fp64": _lib.FP64, "fp32": _lib.FP32, "hilo": _lib.HILO, "s16": _lib.S16}
+_FACES = {"xlo": 0, "xhi": 1, "ylo": 2, "yhi": 3, "zlo": 4, "zhi": 5}
+
+
+def _aligned_workspace(nbytes: int, device) -> tuple[torch.Tensor, int]:
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf.data_ptr() + off
+
+
+class Simulation:
+    """A MacLAB problem on one GPU.
+
+    Parameters follow the paper's statement of a problem (recipe steps
+    (i)-(v) after Eq. (6)): lattice (9 = D2Q9, 19 = D3Q19), node counts
+    (nx, ny, nz) including boundary nodes, lattice size ``dx``, viscosity
+    ``nu``; plus a uniform body force G = -grad p and the storage precision
+    ("fp64", "fp32", "hilo", "s16").
+    """
+
+    def __init__(self, lattice: int, n, dx: float, nu: float, precision: str = "fp32",
+                 body_force=(0.0, 0.0, 0.0), rho_ref: float = 1.0, seed: int = 0, device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("MacLAB needs a GPU: torch.cuda.is_available() is False")
+        self.lib = _lib.load()
+        self.device = torch.device(device if device is not None else "cuda")
+        n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
+        self.q = int(lattice)
+        self.d = 2 if self.q == 9 else 3
+        self.n = n
+        self.N = n[0] * n[1] * n[2]
+        self.precision = precision
+        cfg = _lib.Config()
+        cfg.lattice = self.q
+        cfg.precision = _PRECISIONS[precision]
+        for i in range(3):
+            cfg.n[i] = n[i]
+            cfg.body_force[i] = float(body_force[i]) if i < len(body_force) else 0.0
+        cfg.dx = float(dx)
+        cfg.nu = float(nu)
+        cfg.rho_ref = float(rho_ref)
+        cfg.seed = int(seed)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+        cfg.stream = self.stream.cuda_stream
+        need = self.lib.maclab_workspace_bytes(ctypes.byref(cfg))
+        if need == 0:
+            # let init produce the precise message
+            cfg.workspace = None
+            h = ctypes.c_void_p()
+            _lib.check(self.lib.maclab_init(ctypes.byref(cfg), ctypes.byref(h)))
+        self._ws, ptr = _aligned_workspace(need, self.device)
+        cfg.workspace = ptr
+        cfg.workspace_bytes = need
+        self.cfg = cfg
+        self.h = ctypes.c_void_p()
+        _lib.check(self.lib.maclab_init(ctypes.byref(cfg), ctypes.byref(self.h)))
+
+    # -------------------------------------------------------------- set-up
+    def set_bc(self, face, rho_b: float = 1.0, u_b=(0.0, 0.0, 0.0), periodic: bool = False) -> None:
+        f = _FACES[face] if isinstance(face, str) else int(face)
+        u = (ctypes.c_double * 3)(*[float(v) for v in (tuple(u_b) + (0.0, 0.0, 0.0))[:3]])
+        kind = _lib.PERIODIC if periodic else _lib.FIXED
+        _lib.check(self.lib.maclab_set_bc(self.h, f, kind, float(rho_b), u), self.h)
+
+    def set_fields(self, rho, u) -> None:
+        """rho: N values, u: d*N values (physical units), numpy or torch."""
+        if isinstance(rho, torch.Tensor) and rho.is_cuda:
+            r = rho.to(self.device, torch.float64).contiguous()
+            v = u.to(self.device, torch.float64).contiguous()
+            assert r.numel() == self.N and v.numel() == self.d * self.N
+            _lib.check(self.lib.maclab_set_fields(self.h, r.data_ptr(), v.data_ptr(), 1), self.h)
+            torch.cuda.current_stream(self.device).synchronize()
+        else:
+            r = np.ascontiguousarray(np.asarray(rho, dtype=np.float64).ravel())
+            v = np.ascontiguousarray(np.asarray(u, dtype=np.float64).ravel())
+            assert r.size == self.N and v.size == self.d * self.N
+            _lib.check(self.lib.maclab_set_fields(self.h, r.ctypes.data, v.ctypes.data, 0), self.h)
+
+    # ------------------------------------------------------------ stepping
+    def step(self, n: int = 1) -> None:
+        _lib.check(self.lib.maclab_step(self.h, int(n)), self.h)
+
+    def step_checked(self, n: int, check_every: int) -> int:
+        """Steps with periodic non-finite / Mach checks; raises MaclabError
+        (code ENONFINITE) on failure. Returns the steps completed."""
+        done = ctypes.c_int64(0)
+        rc = self.lib.maclab_step_checked(self.h, int(n), int(check_every), ctypes.byref(done))
+        self.last_done = done.value
+        _lib.check(rc, self.h)
+        return done.value
+
+    # -------------------------------------------------------------- output
+    def fields(self, on_device: bool = False):
+        """Physical (rho, u) as (nz, ny, nx) and (d, nz, ny, nx) float64."""
+        shape = (self.n[2], self.n[1], self.n[0])
+        if on_device:
+            r = torch.empty(shape, dtype=torch.float64, device=self.device)
+            v = torch.empty((self.d,) + shape, dtype=torch.float64, device=self.device)
+            _lib.check(self.lib.maclab_get_fields(self.h, r.data_ptr(), v.data_ptr(), 1), self.h)
+            return r, v
+        r = np.empty(shape)
+        v = np.empty((self.d,) + shape)
+        _lib.check(self.lib.maclab_get_fields(self.h, r.ctypes.data, v.ctypes.data, 0), self.h)
+        return r, v
+
+    def diagnostics(self) -> np.ndarray:
+        """[mass, Px, Py, Pz, kinetic energy, max |u|/e, non-finite count]."""
+        out = np.zeros(7)
+        _lib.check(self.lib.maclab_diagnostics(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self.h)
+        return out
+
+    def params(self) -> dict:
+        out = np.zeros(6)
+        _lib.check(self.lib.maclab_params(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self.h)
+        keys = ("e", "dt", "R_le", "Ma", "steps", "t")
+        return dict(zip(keys, out.tolist()))
+
+    # ---------------------------------------------------------- checkpoint
+    def state_bytes(self) -> int:
+        return int(self.lib.maclab_state_bytes(self.h))
+
+    def save_state(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        assert out.numel() * out.element_size() >= self.state_bytes()
+        _lib.check(self.lib.maclab_save_state(self.h, out.data_ptr()), self.h)
+        return out
+
+    def load_state(self, src: torch.Tensor) -> None:
+        assert src.numel() * src.element_size() >= self.state_bytes()
+        _lib.check(self.lib.maclab_load_state(self.h, src.data_ptr()), self.h)
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.maclab_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/maclab.h declares, sizes workspaces, and rejects
+invalid configurations before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1901_02716_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "maclab.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(maclab_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_what_binding_lists():
+    assert _declared() == sorted(_lib.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def _cfg(**kw):
+    c = _lib.Config()
+    c.lattice = kw.get("lattice", 19)
+    c.precision = kw.get("precision", _lib.FP32)
+    n = kw.get("n", (256, 256, 256))
+    for i in range(3):
+        c.n[i] = n[i]
+    c.dx = kw.get("dx", 1 / 255)
+    c.nu = kw.get("nu", 2.5e-4)
+    c.rho_ref = kw.get("rho_ref", 1.0)
+    c.workspace = kw.get("workspace", None)
+    c.workspace_bytes = kw.get("workspace_bytes", 0)
+    return c
+
+
+def test_workspace_bytes():
+    lib = _lib.load()
+    c = _cfg()
+    need = lib.maclab_workspace_bytes(ctypes.byref(c))
+    N = 256 ** 3
+    # two state buffers of 4 planes of N float32, plus partials and staging
+    assert need >= 2 * 4 * N * 4
+    assert need < 2 * 4 * N * 4 + (16 << 20)
+    c16 = _cfg(precision=_lib.S16)
+    assert lib.maclab_workspace_bytes(ctypes.byref(c16)) < need
+    c2 = _cfg(lattice=9, n=(1024, 1024, 1), precision=_lib.FP64)
+    assert lib.maclab_workspace_bytes(ctypes.byref(c2)) >= 2 * 3 * 1024 * 1024 * 8
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(lattice=15), _lib.EUNSUPPORTED),
+    (dict(precision=7), _lib.EUNSUPPORTED),
+    (dict(dx=0.0), _lib.EINVAL),
+    (dict(nu=-1.0), _lib.EINVAL),
+    (dict(rho_ref=0.0), _lib.EINVAL),
+    (dict(n=(0, 4, 4)), _lib.EINVAL),
+    (dict(lattice=9, n=(8, 8, 2)), _lib.EINVAL),
+    (dict(), _lib.EWORKSPACE),                      # no workspace
+    (dict(workspace=4096, workspace_bytes=16), _lib.EWORKSPACE),  # too small
+    (dict(workspace=4100, workspace_bytes=1 << 40), _lib.EWORKSPACE),  # misaligned
+])
+def test_init_rejects_invalid_config_without_gpu(kw, code):
+    lib = _lib.load()
+    c = _cfg(**kw)
+    assert lib.maclab_workspace_bytes(ctypes.byref(c)) == 0 or code == _lib.EWORKSPACE
+    h = ctypes.c_void_p(123)
+    rc = lib.maclab_init(ctypes.byref(c), ctypes.byref(h))
+    assert rc == code
+    assert h.value is None
+    assert lib.maclab_last_error(None)
+
+
+def test_null_handle_calls_fail_cleanly():
+    lib = _lib.load()
+    assert lib.maclab_step(None, 1) == _lib.EINVAL
+    assert lib.maclab_state_bytes(None) == 0
+    lib.maclab_destroy(None)
+    assert b"NULL" in lib.maclab_last_error(None)

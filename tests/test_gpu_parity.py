@@ -1,0 +1,243 @@
+"""GPU parity: the HIP MacLAB step (through the C ABI) against the FP64 oracle.
+
+Tolerances (relative L2 over all nodes, physical units):
+  FP64 storage 1e-12, FP32 1e-5, HILO and S16 2e-3.
+Boundary values, determinism and checkpoint resume are bitwise.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1901_02716_amd import MaclabError, Simulation, _lib, workloads
+from conftest import rel_l2, to_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "hilo": 2e-3, "s16": 2e-3}
+
+
+def make_sim(case, precision, seed=0):
+    sim = Simulation(case.q, case.n, case.dx, case.nu, precision=precision, body_force=case.G, seed=seed)
+    sim.set_fields(case.rho, case.u)
+    for face, (rb, ub) in case.fixed.items():
+        sim.set_bc(face, rb, ub)
+    return sim
+
+
+def run_both(case, precision, steps, seed=0):
+    print(f"[parity] {case.name} q={case.q} n={case.n} {precision} steps={steps}", flush=True)
+    sim = make_sim(case, precision, seed)
+    sim.step(steps)
+    rho, u = sim.fields()
+    orho, ou = oracle.run(to_problem(case), case.rho, case.u, steps)
+    return sim, (rho, u), (orho, ou)
+
+
+def test_taylor_green_fp64_full_size():
+    """64^2 periodic vortex, nu = 0.01, U0 = 0.01, 1000 steps."""
+    nu, n, U0, steps = 0.01, 64, 0.01, 1000
+    e = oracle.particle_speed(nu, 1.0 / n)
+    case = workloads.taylor_green(n, nu, U0, e=e, steps=steps)
+    _, (rho, u), (orho, ou) = run_both(case, "fp64", steps)
+    assert rel_l2(u, ou) < 1e-12
+    assert rel_l2(rho, orho) < 1e-12
+    # and the decay against the continuous solution is the oracle's
+    t = steps * case.dx / e
+    ua = workloads.taylor_green_analytic(case, t, U0)
+    assert rel_l2(u, ua) == pytest.approx(rel_l2(ou, ua), rel=1e-9)
+
+
+@pytest.mark.parametrize("q,n", [(9, (37, 23, 1)), (19, (13, 11, 9)), (9, (64, 64, 1)), (19, (64, 8, 5))])
+@pytest.mark.parametrize("force", [False, True])
+def test_random_periodic_fp64(q, n, force):
+    case = workloads.random_field(q, n, seed=21)
+    if force:
+        case.G = (0.3, -0.2, 0.1)
+    _, (rho, u), (orho, ou) = run_both(case, "fp64", 25)
+    assert rel_l2(u, ou) < 1e-12
+    assert rel_l2(rho, orho) < 1e-12
+
+
+CAVITIES = [
+    ("c2d_ragged", lambda: workloads.cavity_2d(n=45, Re=40.0, U=0.1), 300),
+    ("c2d_128", lambda: workloads.cavity_2d(n=128, Re=200.0, U=0.1), 600),
+    ("c3d_ragged", lambda: workloads.cavity_3d(n=19, Re=25.0, U=0.1), 150),
+    ("c3d_32", lambda: workloads.cavity_3d(n=32, Re=48.7, U=0.1), 150),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "hilo", "s16"])
+@pytest.mark.parametrize("name,mk,steps", CAVITIES, ids=[c[0] for c in CAVITIES])
+def test_cavity_parity(name, mk, steps, precision):
+    case = mk()
+    _, (rho, u), (orho, ou) = run_both(case, precision, steps, seed=5)
+    eu, er = rel_l2(u, ou), rel_l2(rho, orho)
+    print(f"  relL2 u={eu:.3e} rho={er:.3e}", flush=True)
+    assert eu < TOL[precision]
+    assert er < TOL[precision]
+
+
+def test_non_cubic_mixed_boundaries_fp64():
+    """Walls in x and z, periodic in y, with a body force along y."""
+    case = workloads.random_field(19, (11, 16, 9), seed=4, amp=0.02)
+    for f in ("xlo", "xhi", "zlo"):
+        case.fixed[f] = (1.0, (0.0, 0.0, 0.0))
+    case.fixed["zhi"] = (1.002, (0.05, 0.01, 0.0))
+    case.G = (0.0, 0.2, 0.0)
+    _, (rho, u), (orho, ou) = run_both(case, "fp64", 40)
+    assert rel_l2(u, ou) < 1e-12
+    assert rel_l2(rho, orho) < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_poiseuille_channel(precision):
+    """Test 2 of the paper: dp/dx = -1e-4, nu = 0.001, from rest."""
+    case = workloads.channel(nu=0.001, u0=0.1, dpdx=-1e-4)
+    _, (rho, u), (orho, ou) = run_both(case, precision, 500)
+    assert rel_l2(u, ou) < TOL[precision]
+    # the exact steady profile is a fixed point on the GPU too
+    prof = workloads.channel_profile(case, 0.1, -1e-4)
+    case.u[0] = prof[None, :, None]
+    sim = make_sim(case, precision)
+    sim.step(100)
+    _, u2 = sim.fields()
+    assert np.abs(u2[0, 0] - prof[:, None]).max() < (1e-12 if precision == "fp64" else 2e-6)
+
+
+@pytest.mark.parametrize("n", [(1, 1, 1), (1, 5, 3), (2, 3, 1), (3, 1, 1)])
+def test_degenerate_periodic_shapes(n):
+    """Axes of one or two nodes: every link wraps onto the node itself or
+    its single neighbour."""
+    q = 9 if n[2] == 1 else 19
+    case = workloads.random_field(q, n, seed=8)
+    _, (rho, u), (orho, ou) = run_both(case, "fp64", 6)
+    assert rel_l2(u, ou) < 1e-12
+    assert rel_l2(rho, orho) < 1e-12
+
+
+def test_long_thin_channel():
+    """A 4097 x 3 channel: ragged in x, a single interior row in y."""
+    case = workloads.channel(nx=4097, ny=3, dx=0.01, nu=0.002, u0=0.05, dpdx=-1e-3)
+    _, (rho, u), (orho, ou) = run_both(case, "fp64", 30)
+    assert rel_l2(u, ou) < 1e-12
+
+
+def test_boundary_nodes_bitwise_unchanged():
+    case = workloads.cavity_3d(n=17, Re=30.0, U=0.1)
+    sim = make_sim(case, "fp32")
+    s0 = sim.save_state().cpu().numpy().copy()
+    sim.step(7)
+    s1 = sim.save_state().cpu().numpy()
+    N = sim.N
+    plane = s0.size // 4  # 4 planes in bytes
+    mask = np.zeros(case.shape, dtype=bool)
+    mask[0] = mask[-1] = True
+    mask[:, 0] = mask[:, -1] = True
+    mask[:, :, 0] = mask[:, :, -1] = True
+    idx = np.flatnonzero(mask.ravel())
+    for f in range(4):
+        a = s0[f * plane:f * plane + 4 * N].view(np.uint32)
+        b = s1[f * plane:f * plane + 4 * N].view(np.uint32)
+        assert np.array_equal(a[idx], b[idx])
+        if f == 1:
+            assert not np.array_equal(a, b)
+    rho, u = sim.fields()
+    e = sim.params()["e"]
+    assert np.all(u[0, -1, 1:-1, 1:-1] == float(np.float32(0.1 / e)) * e)
+    assert np.all(u[0, -1, 0, :] == 0.0)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "s16"])
+def test_deterministic_rerun(precision):
+    case = workloads.cavity_3d(n=24, Re=40.0, U=0.1)
+    a = make_sim(case, precision, seed=9)
+    a.step(20)
+    b = make_sim(case, precision, seed=9)
+    b.step(20)
+    assert torch.equal(a.save_state(), b.save_state())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "hilo", "s16"])
+def test_checkpoint_resume_bitwise(precision):
+    case = workloads.cavity_2d(n=40, Re=30.0, U=0.1)
+    a = make_sim(case, precision, seed=3)
+    a.step(10)
+    ck = a.save_state().clone()
+    a.step(15)
+    ref = a.save_state().clone()
+    b = make_sim(case, precision, seed=3)
+    b.step(10)  # same step counter as a at the checkpoint
+    b.step(0)
+    b.load_state(ck)
+    b.step(15)
+    assert torch.equal(b.save_state(), ref)
+
+
+def test_diagnostics_match_oracle():
+    case = workloads.random_field(19, (20, 18, 16), seed=12)
+    case.G = (0.1, 0.0, -0.05)
+    sim, (rho, u), (orho, ou) = run_both(case, "fp64", 10)
+    dg = sim.diagnostics()
+    do = oracle.diagnostics(to_problem(case), orho, ou)
+    for i in (0, 1, 2, 3, 4, 5):
+        assert dg[i] == pytest.approx(do[i], rel=1e-11, abs=1e-13)
+    assert dg[6] == do[6] == 0
+
+
+def test_checked_step_reports_blow_up():
+    """A 64^2 cavity at R_le = 79 violates the Mach condition: both the
+    oracle and the GPU report non-finite values or max |u|/e >= 1."""
+    case = workloads.cavity_2d(n=64, Re=5000.0, U=0.1)
+    sim = make_sim(case, "fp64")
+    assert sim.params()["R_le"] == pytest.approx(0.1 * case.dx / case.nu)
+    with pytest.raises(MaclabError) as ei:
+        sim.step_checked(200, 10)
+    assert ei.value.code == _lib.ENONFINITE
+    p = to_problem(case)
+    orho, ou = oracle.run(p, case.rho, case.u, sim.last_done)
+    do = oracle.diagnostics(p, orho, ou)
+    assert do[6] > 0 or do[5] >= 1.0
+
+
+def test_mismatched_faces_rejected():
+    case = workloads.cavity_2d(n=16, Re=10.0, U=0.1)
+    sim = make_sim(case, "fp32")
+    sim.set_bc("xhi", periodic=True)
+    with pytest.raises(MaclabError) as ei:
+        sim.step(1)
+    assert ei.value.code == _lib.EINVAL
+
+
+# ------------------------------------------------- full-size sampled parity
+
+@pytest.mark.parametrize("name,mk,precision,tol", [
+    ("cube256_fp32", lambda: workloads.cavity_3d(n=256, Re=400.0, U=0.1), "fp32", 1e-5),
+    ("cavity1024_fp64", lambda: workloads.cavity_2d(n=1024, Re=1000.0, U=0.1), "fp64", 1e-12),
+    ("cavity1024_fp32", lambda: workloads.cavity_2d(n=1024, Re=1000.0, U=0.1), "fp32", 1e-5),
+    ("periodic512_fp32", lambda: workloads.adjoint_case()[0], "fp32", 1e-5),
+])
+def test_full_size_step_on_sampled_nodes(name, mk, precision, tol):
+    """At the benchmark sizes: after a few GPU steps, the next GPU step is
+    compared with the oracle's step from the same state on sampled nodes."""
+    case = mk()
+    print(f"[full-size] {name}", flush=True)
+    sim = make_sim(case, precision)
+    sim.step(5)
+    rho, u = sim.fields()
+    sim.step(1)
+    rho1, u1 = sim.fields()
+    p = to_problem(case)
+    rng = np.random.default_rng(0)
+    N = p.N
+    nodes = np.unique(np.concatenate([rng.choice(N, 20000, replace=False), np.arange(0, min(N, 4096)),
+                                      np.arange(N - 4096, N)]))
+    orho, ou = oracle.step_at(p, rho.ravel(), u.reshape(case.d, -1), nodes)
+    gr = rho1.ravel()[nodes]
+    gu = u1.reshape(case.d, -1)[:, nodes]
+    # compare the change of the step, which is the part the kernel computes
+    du_o = ou - u.reshape(case.d, -1)[:, nodes]
+    du_g = gu - u.reshape(case.d, -1)[:, nodes]
+    assert rel_l2(gu, ou) < tol
+    assert rel_l2(gr, orho) < tol
+    assert rel_l2(du_g, du_o) < (1e-9 if precision == "fp64" else 1e-3)

@@ -19,7 +19,7 @@ MUTANTS = {
     "push_not_pull": ("int64_t si = wrap(i - c[a][0], nx);", "int64_t si = wrap(i + c[a][0], nx);"),
     "momentum_component": ("m[cc] += e * (double)c[a][cc] * f;", "m[cc] += e * (double)c[a][(cc + 1) % d] * f;"),
     "force_sign": ("m[cc] / r + dt * p->G[cc] / r", "m[cc] / r - dt * p->G[cc] / r"),
-    "old_density": ("m[cc] / r + dt", "m[cc] / rho[x] + dt"),
+    "old_density": ("m[cc] / r + dt", "m[cc] / rho[i + nx * (j + ny * k)] + dt"),
     "viscosity_map": ("return 6.0 * nu / dx;", "return 3.0 * nu / dx;"),
     "d3q19_weight": ("1.0 / 18.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,\n    1.0 / 36.0, 1.0 / 36.0",
                      "1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,\n    1.0 / 36.0, 1.0 / 36.0"),
@@ -28,7 +28,8 @@ MUTANTS = {
     "corner_owner": ("for (int f = 0; f < 6; ++f) {\n    if (p->face_kind[f] != ORACLE_FIXED) continue;",
                      "for (int f = 5; f >= 0; --f) {\n    if (p->face_kind[f] != ORACLE_FIXED) continue;"),
     "energy_half": ("nsum_add(&E, 0.5 * rho[x] * uu);", "nsum_add(&E, rho[x] * uu);"),
-    "fixed_nodes_updated": ("if (fixed_face(p, i, j, k) >= 0) {", "if (fixed_face(p, i, j, k) >= 7) {"),
+    "fixed_nodes_updated": ("if (fixed_face(p, i, j, k) >= 0) {\n          /* Recipe step (iv)",
+                            "if (fixed_face(p, i, j, k) >= 7) {\n          /* Recipe step (iv)"),
 }
 
 

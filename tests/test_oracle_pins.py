@@ -373,3 +373,18 @@ def test_unstable_cavity_is_detected(oracle_lib):
     rho, u = oracle.run(p, case.rho, case.u, 200)
     d = oracle.diagnostics(p, rho, u)
     assert d[6] > 0 or d[5] >= 1.0
+
+
+def test_step_at_matches_full_step(oracle_lib):
+    """The sampled-node evaluation is the full step restricted to the sample
+    (walled cube and periodic square, including fixed nodes)."""
+    for case in (workloads.cavity_3d(n=9, Re=10.0, U=0.1), workloads.random_field(9, (11, 7, 1), seed=2)):
+        p = to_problem(case)
+        rho0, u0 = case.rho.copy(), case.u.copy()
+        oracle.impose_boundary(p, rho0, u0)
+        rho1, u1 = oracle.run(p, rho0, u0, 1)
+        nodes = np.random.default_rng(0).choice(p.N, size=40, replace=False)
+        nodes[0] = 0  # a corner (fixed in the cube)
+        r, u = oracle.step_at(p, rho0, u0, nodes)
+        assert np.array_equal(r, rho1.ravel()[nodes])
+        assert np.array_equal(u, u1.reshape(case.d, -1)[:, nodes])
