@@ -1,0 +1,201 @@
+"""Benchmark of the MacLAB time step on one MI355X.
+
+Default workload: D3Q19 lid-driven cube, 256^3 nodes including walls,
+Re = 400 (lid u = (0.1, 0, 0) on z = 1), FP32 storage and arithmetic. One
+step is one launch of the step kernel over the lattice; MLUPS counts the
+updated (non-wall) nodes, 254^3 per step. The split-storage variants (S16 =
+scaled binary16 with stochastic rounding, HILO = bfloat16 hi+lo) are timed on
+the same lattice and reported beside it.
+
+Output: one JSON line (rank 0) with the metric, the roofline of the step
+kernel (algorithmic bytes per launch / measured launch time against 8 TB/s),
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import glob
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+WORKLOADS = {
+    "cube256": dict(desc="D3Q19 lid-driven cube 256^3 Re=400", q=19, n=256, Re=400.0, U=0.1),
+    "cube64": dict(desc="D3Q19 lid-driven cube 64^3 Re=98.8", q=19, n=64, Re=98.8, U=0.1),
+    "cavity1024": dict(desc="D2Q9 lid-driven cavity 1024^2 Re=1000", q=9, n=1024, Re=1000.0, U=0.1),
+}
+BYTES = {"fp64": 8, "fp32": 4, "hilo": 4, "s16": 2}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1901_02716_amd", "csrc", "*"))):
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def make_case(wl):
+    from paper_1901_02716_amd import workloads
+
+    if wl["q"] == 19:
+        return workloads.cavity_3d(n=wl["n"], Re=wl["Re"], U=wl["U"])
+    return workloads.cavity_2d(n=wl["n"], Re=wl["Re"], U=wl["U"])
+
+
+def updated_nodes(case) -> int:
+    n = 1
+    for ax in range(case.d):
+        walled = any(f[0] == "xyz"[ax] for f in case.fixed)
+        n *= case.n[ax] - 2 if walled else case.n[ax]
+    return n
+
+
+def time_variant(case, precision, steps, warmup):
+    import torch
+
+    from paper_1901_02716_amd import Simulation
+
+    sim = Simulation(case.q, case.n, case.dx, case.nu, precision=precision, seed=1)
+    sim.set_fields(case.rho, case.u)
+    for face, (rb, ub) in case.fixed.items():
+        sim.set_bc(face, rb, ub)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(sim.stream)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    stop.record(sim.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop)
+    d = sim.diagnostics()
+    sim.close()
+    return ms / steps, wall, d
+
+
+def cpu_baseline(case, steps: int):
+    """The FP64 oracle on `steps` steps of the same lattice, one thread."""
+    import oracle
+
+    p = oracle.Problem(case.q, case.n, case.dx, case.nu)
+    for face, (rb, ub) in case.fixed.items():
+        p.set_fixed(face, rb, ub)
+    oracle.build()
+    t0 = time.perf_counter()
+    oracle.run(p, case.rho, case.u, steps)
+    dt = time.perf_counter() - t0
+    return updated_nodes(case) * steps / dt / 1e6, dt
+
+
+def load_traffic(workload: str, precision: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(f"{workload}:{precision}")
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="cube256", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=sorted(BYTES))
+    ap.add_argument("--variants", default="s16,hilo", help="extra storage variants to time ('' for none)")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-copy-mib", type=int, default=0,
+                    help="after timing, run one torch copy of this many MiB (counter calibration)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the step would shard as z-slabs with one-plane halo exchange).", file=sys.stderr)
+        return 2
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    wl = WORKLOADS[args.workload]
+    case = make_case(wl)
+    lu = updated_nodes(case)
+    d = case.d
+    ms, wall, diag = time_variant(case, args.precision, args.steps, args.warmup)
+    mlups = lu / (ms * 1e-3) / 1e6
+    b_lu = 2 * (d + 1) * BYTES[args.precision]
+    achieved = b_lu * lu / (ms * 1e-3) / 1e9
+    traffic = load_traffic(args.workload, args.precision)
+
+    variants = {}
+    for v in [s for s in args.variants.split(",") if s and s != args.precision]:
+        vms, _, vd = time_variant(case, v, args.steps, args.warmup)
+        vm = lu / (vms * 1e-3) / 1e6
+        variants[v] = {"mlups": round(vm, 1), "ms_per_step": round(vms, 5),
+                       "vs_" + args.precision: round(vm / mlups, 3),
+                       "hbm_frac": round(2 * (d + 1) * BYTES[v] * lu / (vms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cm, cdt = cpu_baseline(case, args.cpu_steps)
+        cpu = {"value": round(cm, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+               "sample": f"{args.cpu_steps} FP64 steps of the same {wl['desc']} lattice "
+                         f"({args.cpu_steps * lu} lattice updates, {cdt:.1f} s, single thread)"}
+
+    if args.profile_copy_mib > 0:
+        n = args.profile_copy_mib << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": "MLUPS + HBM-roofline fraction, D3Q19 256^3 FP32 vs split-BF16; adjoint/fwd cost",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "hilo": "f32 (bf16x2 storage)", "s16": "f32 (f16 storage)"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"{wl['desc']} {args.precision}", "lattice": "D3Q19" if d == 3 else "D2Q9",
+                   "nodes": list(case.n), "updated_nodes_per_step": lu, "storage": args.precision,
+                   "bytes_per_lattice_update": b_lu},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+        "cpu_baseline": cpu,
+        "variants": variants,
+        "diagnostics_after": {"mass": diag[0], "max_u_over_e": diag[5], "nonfinite": diag[6]},
+        "wall_s": round(wall, 3),
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
