@@ -59,7 +59,7 @@ def updated_nodes(case) -> int:
     return n
 
 
-def time_variant(case, precision, steps, warmup):
+def time_variant(case, precision, steps, warmup, autotune=True, tiling=None):
     import torch
 
     from paper_1901_02716_amd import Simulation
@@ -68,6 +68,11 @@ def time_variant(case, precision, steps, warmup):
     sim.set_fields(case.rho, case.u)
     for face, (rb, ub) in case.fixed.items():
         sim.set_bc(face, rb, ub)
+    if tiling is not None:
+        sim.set_tiling(*tiling)
+    elif autotune:
+        sim.autotune(reps=5)
+    sim.tiling_used = sim.tiling()
     sim.step(warmup)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -80,6 +85,7 @@ def time_variant(case, precision, steps, warmup):
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(stop)
     d = sim.diagnostics()
+    d = {"diag": d, "tiling": sim.tiling_used}
     sim.close()
     return ms / steps, wall, d
 
@@ -123,6 +129,8 @@ def main(argv=None):
     ap.add_argument("--variants", default="s16,hilo", help="extra storage variants to time ('' for none)")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default tiling")
+    ap.add_argument("--tiling", default="", help="W,nyb,nzb of the fast kernel (skips autotuning)")
     ap.add_argument("--profile-copy-mib", type=int, default=0,
                     help="after timing, run one torch copy of this many MiB (counter calibration)")
     args = ap.parse_args(argv)
@@ -141,7 +149,9 @@ def main(argv=None):
     case = make_case(wl)
     lu = updated_nodes(case)
     d = case.d
-    ms, wall, diag = time_variant(case, args.precision, args.steps, args.warmup)
+    tiling = tuple(int(v) for v in args.tiling.split(",")) if args.tiling else None
+    ms, wall, info = time_variant(case, args.precision, args.steps, args.warmup, not args.no_autotune, tiling)
+    diag = info["diag"]
     mlups = lu / (ms * 1e-3) / 1e6
     b_lu = 2 * (d + 1) * BYTES[args.precision]
     achieved = b_lu * lu / (ms * 1e-3) / 1e9
@@ -149,9 +159,9 @@ def main(argv=None):
 
     variants = {}
     for v in [s for s in args.variants.split(",") if s and s != args.precision]:
-        vms, _, vd = time_variant(case, v, args.steps, args.warmup)
+        vms, _, vd = time_variant(case, v, args.steps, args.warmup, not args.no_autotune, tiling)
         vm = lu / (vms * 1e-3) / 1e6
-        variants[v] = {"mlups": round(vm, 1), "ms_per_step": round(vms, 5),
+        variants[v] = {"mlups": round(vm, 1), "ms_per_step": round(vms, 5), "tiling": vd["tiling"],
                        "vs_" + args.precision: round(vm / mlups, 3),
                        "hbm_frac": round(2 * (d + 1) * BYTES[v] * lu / (vms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
@@ -184,7 +194,7 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": f"{wl['desc']} {args.precision}", "lattice": "D3Q19" if d == 3 else "D2Q9",
                    "nodes": list(case.n), "updated_nodes_per_step": lu, "storage": args.precision,
-                   "bytes_per_lattice_update": b_lu},
+                   "bytes_per_lattice_update": b_lu, "tiling": info["tiling"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "cpu_baseline": cpu,

@@ -147,6 +147,21 @@ size_t maclab_state_bytes(maclab_t h);
 int maclab_save_state(maclab_t h, void* dst_device);
 int maclab_load_state(maclab_t h, const void* src_device);
 
+/* Kernel tiling. out[4] = {kernel, W, nyb, nzb}: kernel 0 is the general
+ * kernel (any shape; no tiling), kernel 1 the fast D3Q19 kernel (x extent 64,
+ * 128 or 256; FP32 arithmetic) whose workgroups own W consecutive output rows
+ * (one wavefront per x-row) of an nyb x nzb grid of balanced (y, z) tiles.
+ * set_tiling validates (W in {4, 6, 8, 10, 12}, ceil(rows / nyb) <= W) and
+ * returns MACLAB_EUNSUPPORTED for lattices on the general kernel. */
+int maclab_get_tiling(maclab_t h, int out[4]);
+int maclab_set_tiling(maclab_t h, int W, int nyb, int nzb);
+
+/* Times the candidate tilings of this lattice (each launched `reps` times
+ * from the current state into the spare buffer, so the simulation does not
+ * advance) and keeps the fastest; *best_ms (may be NULL) receives its time
+ * per step. Synchronises. */
+int maclab_autotune(maclab_t h, int reps, double* best_ms);
+
 /* Releases the handle (not the caller's memory). NULL is ignored. */
 void maclab_destroy(maclab_t h);
 

@@ -17,8 +17,8 @@ PERIODIC, FIXED = 0, 1
 SYMBOLS = (
     "maclab_workspace_bytes", "maclab_init", "maclab_set_bc", "maclab_set_fields", "maclab_step",
     "maclab_step_checked", "maclab_get_fields", "maclab_diagnostics", "maclab_params",
-    "maclab_state_bytes", "maclab_save_state", "maclab_load_state", "maclab_destroy",
-    "maclab_last_error",
+    "maclab_state_bytes", "maclab_save_state", "maclab_load_state", "maclab_get_tiling",
+    "maclab_set_tiling", "maclab_autotune", "maclab_destroy", "maclab_last_error",
 )
 
 
@@ -72,6 +72,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.maclab_state_bytes.argtypes = [H]
     lib.maclab_save_state.argtypes = [H, ctypes.c_void_p]
     lib.maclab_load_state.argtypes = [H, ctypes.c_void_p]
+    lib.maclab_get_tiling.argtypes = [H, ctypes.POINTER(ctypes.c_int)]
+    lib.maclab_set_tiling.argtypes = [H, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.maclab_autotune.argtypes = [H, ctypes.c_int, dp]
     lib.maclab_destroy.restype = None
     lib.maclab_destroy.argtypes = [H]
     lib.maclab_last_error.restype = ctypes.c_char_p

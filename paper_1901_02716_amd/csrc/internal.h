@@ -46,9 +46,17 @@ hipError_t launch_decode(const Layout& L, double* dst, const void* plane_src, in
 hipError_t launch_diagnostics(const Layout& L, const void* state, double rho_ref, double e, double* partials,
                               double* result, hipStream_t s);
 
-// Fast paths (kernels_fast.hip). `supported` tells whether a fast kernel
-// handles the layout and boundary kinds; launch enqueues one step.
+// Fast D3Q19 path (kernels_fast.hip). `supported` tells whether the fast
+// kernel handles the layout; a FastShape is its tiling: W output rows per
+// workgroup (one wavefront each), nyb x nzb workgroups with balanced ranges.
+struct FastShape {
+  int W = 8, nyb = 1, nzb = 1;
+};
 bool fast_step_supported(const Layout& L, const StepParams& p);
-hipError_t launch_step_fast(const Layout& L, const void* src, void* dst, const StepParams& p, hipStream_t s);
+bool fast_shape_valid(const Layout& L, const StepParams& p, const FastShape& sh);
+FastShape fast_default_shape(const Layout& L, const StepParams& p, int cus);
+int fast_candidates(const Layout& L, const StepParams& p, int cus, FastShape* out, int max_out);
+hipError_t launch_step_fast(const Layout& L, const void* src, void* dst, const StepParams& p, const FastShape& sh,
+                            hipStream_t s);
 
 }  // namespace maclab

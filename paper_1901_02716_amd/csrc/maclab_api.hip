@@ -25,6 +25,9 @@ struct maclab_s {
   FaceValues fv;
   double e = 0, dt = 0;
   int64_t steps = 0;
+  int cus = 256;               // compute units of the device
+  FastShape shape;             // tiling of the fast kernel
+  bool shape_set = false;      // chosen by maclab_set_tiling / maclab_autotune
   std::string err;
 };
 
@@ -190,6 +193,12 @@ int maclab_init(const maclab_config* cfg, maclab_t* out) {
     h->fv.rho[f] = cfg->rho_ref;
     for (int c = 0; c < 3; ++c) h->fv.u[f][c] = 0.0;
   }
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      h->cus = cus;
+  }
   h->e = 6.0 * cfg->nu / cfg->dx;  // Eq. (6)
   h->dt = cfg->dx / h->e;          // text after Eq. (6)
   // state at rest: zero deviation and zero velocity in every codec
@@ -257,12 +266,16 @@ int maclab_step(maclab_t h, int64_t n) {
   if (rc) return rc;
   StepParams p = make_params(h);
   const bool fast = fast_step_supported(h->L, p);
+  if (fast && !(h->shape_set && fast_shape_valid(h->L, p, h->shape))) {
+    h->shape = fast_default_shape(h->L, p, h->cus);
+    h->shape_set = false;
+  }
   for (int64_t s = 0; s < n; ++s) {
     p.step = (uint64_t)h->steps;
     const void* src = h->state[h->cur];
     void* dst = h->state[h->cur ^ 1];
     if (fast)
-      HIP_TRY(h, launch_step_fast(h->L, src, dst, p, h->stream));
+      HIP_TRY(h, launch_step_fast(h->L, src, dst, p, h->shape, h->stream));
     else
       HIP_TRY(h, launch_step_generic(h->L, src, dst, p, h->stream));
     h->cur ^= 1;
@@ -361,6 +374,101 @@ int maclab_load_state(maclab_t h, const void* src) {
   if (!src) return fail(h, MACLAB_EINVAL, "src is NULL");
   HIP_TRY(h, hipMemcpyAsync(h->state[0], src, h->L.state_bytes, hipMemcpyDeviceToDevice, h->stream));
   HIP_TRY(h, hipMemcpyAsync(h->state[1], src, h->L.state_bytes, hipMemcpyDeviceToDevice, h->stream));
+  return MACLAB_OK;
+}
+
+int maclab_get_tiling(maclab_t h, int out[4]) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!out) return fail(h, MACLAB_EINVAL, "out is NULL");
+  StepParams p = make_params(h);
+  if (!fast_step_supported(h->L, p)) {
+    out[0] = 0;
+    out[1] = out[2] = out[3] = 0;
+    return MACLAB_OK;
+  }
+  const FastShape sh = (h->shape_set && fast_shape_valid(h->L, p, h->shape)) ? h->shape
+                                                                             : fast_default_shape(h->L, p, h->cus);
+  out[0] = 1;
+  out[1] = sh.W;
+  out[2] = sh.nyb;
+  out[3] = sh.nzb;
+  return MACLAB_OK;
+}
+
+int maclab_set_tiling(maclab_t h, int W, int nyb, int nzb) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  StepParams p = make_params(h);
+  if (!fast_step_supported(h->L, p))
+    return fail(h, MACLAB_EUNSUPPORTED, "this lattice runs the general kernel, which has no tiling");
+  FastShape sh{W, nyb, nzb};
+  if (!fast_shape_valid(h->L, p, sh))
+    return fail(h, MACLAB_EINVAL, "invalid tiling W=%d nyb=%d nzb=%d", W, nyb, nzb);
+  h->shape = sh;
+  h->shape_set = true;
+  return MACLAB_OK;
+}
+
+int maclab_autotune(maclab_t h, int reps, double* best_ms) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (reps < 1) return fail(h, MACLAB_EINVAL, "reps must be >= 1");
+  int rc = check_faces(h);
+  if (rc) return rc;
+  StepParams p = make_params(h);
+  const void* src = h->state[h->cur];
+  void* dst = h->state[h->cur ^ 1];  // scratch output: the state is not advanced
+  const bool fast = fast_step_supported(h->L, p);
+  FastShape cand[16];
+  int nc = 0;
+  if (fast) {
+    cand[nc++] = fast_default_shape(h->L, p, h->cus);
+    FastShape more[16];
+    const int nm = fast_candidates(h->L, p, h->cus, more, 16);
+    for (int i = 0; i < nm && nc < 16; ++i) {
+      bool dup = false;
+      for (int j = 0; j < nc; ++j)
+        dup |= cand[j].W == more[i].W && cand[j].nyb == more[i].nyb && cand[j].nzb == more[i].nzb;
+      if (!dup) cand[nc++] = more[i];
+    }
+  } else {
+    nc = 1;
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(h, hipEventCreate(&e0));
+  hipError_t ee = hipEventCreate(&e1);
+  if (ee != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(h, MACLAB_EHIP, "hipEventCreate: %s", hipGetErrorString(ee));
+  }
+  double best = 1e300;
+  int best_i = 0;
+  hipError_t err = hipSuccess;
+  for (int i = 0; i < nc && err == hipSuccess; ++i) {
+    auto launch = [&]() {
+      return fast ? launch_step_fast(h->L, src, dst, p, cand[i], h->stream)
+                  : launch_step_generic(h->L, src, dst, p, h->stream);
+    };
+    if ((err = launch()) != hipSuccess) break;  // warm-up
+    if ((err = hipEventRecord(e0, h->stream)) != hipSuccess) break;
+    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch();
+    if (err != hipSuccess) break;
+    if ((err = hipEventRecord(e1, h->stream)) != hipSuccess) break;
+    if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+    float ms = 0;
+    if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+    const double per = ms / reps;
+    if (per < best) {
+      best = per;
+      best_i = i;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(h, MACLAB_EHIP, "maclab_autotune: %s", hipGetErrorString(err));
+  if (fast) {
+    h->shape = cand[best_i];
+    h->shape_set = true;
+  }
+  if (best_ms) *best_ms = best;
   return MACLAB_OK;
 }
 

@@ -132,6 +132,21 @@ class Simulation:
         keys = ("e", "dt", "R_le", "Ma", "steps", "t")
         return dict(zip(keys, out.tolist()))
 
+    # -------------------------------------------------------------- tiling
+    def tiling(self) -> dict:
+        out = (ctypes.c_int * 4)()
+        _lib.check(self.lib.maclab_get_tiling(self.h, out), self.h)
+        return {"kernel": ("general", "fast3d")[out[0]], "W": out[1], "nyb": out[2], "nzb": out[3]}
+
+    def set_tiling(self, W: int, nyb: int, nzb: int) -> None:
+        _lib.check(self.lib.maclab_set_tiling(self.h, int(W), int(nyb), int(nzb)), self.h)
+
+    def autotune(self, reps: int = 10) -> float:
+        """Picks the fastest tiling (the state does not advance); returns ms/step."""
+        best = ctypes.c_double(0.0)
+        _lib.check(self.lib.maclab_autotune(self.h, int(reps), ctypes.byref(best)), self.h)
+        return best.value
+
     # ---------------------------------------------------------- checkpoint
     def state_bytes(self) -> int:
         return int(self.lib.maclab_state_bytes(self.h))

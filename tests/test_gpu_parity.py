@@ -307,3 +307,69 @@ def test_fast_path_boundaries_untouched():
         a = s0[f * pb:f * pb + 4 * N].view(np.uint32)
         b = s1[f * pb:f * pb + 4 * N].view(np.uint32)
         assert np.array_equal(a[idx], b[idx])
+
+
+def _tilings(nyo, nzo):
+    out = []
+    for W in (4, 6, 8, 10, 12):
+        nyb = -(-nyo // W)
+        for nzb in sorted({1, 3, nzo}):
+            out.append((W, nyb, nzb))
+    out.append((4, nyo, 2))      # one row per block, idle wavefronts
+    out.append((12, nyo, nzo))  # one row and one plane per block
+    return out
+
+
+@pytest.mark.parametrize("name,nx,nyz,walls,G", [FAST[0], FAST[1], FAST[3]], ids=[FAST[i][0] for i in (0, 1, 3)])
+def test_fast_path_every_tiling_is_bitwise_identical(name, nx, nyz, walls, G):
+    """The tiling only changes which workgroup computes a node, not the
+    order of its sums: every valid tiling gives the same bits, and they
+    match the oracle."""
+    case = _fast_case(nx, nyz, walls, G)
+    nyo = nyz[0] - 2 if "y" in walls else nyz[0]
+    nzo = nyz[1] - 2 if "z" in walls else nyz[1]
+    ref = None
+    for W, nyb, nzb in _tilings(nyo, nzo):
+        sim = make_sim(case, "fp32")
+        sim.set_tiling(W, nyb, nzb)
+        assert sim.tiling() == {"kernel": "fast3d", "W": W, "nyb": nyb, "nzb": nzb}
+        sim.step(6)
+        st = sim.save_state()
+        if ref is None:
+            ref = st.clone()
+            rho, u = sim.fields()
+            orho, ou = oracle.run(to_problem(case), case.rho, case.u, 6)
+            assert rel_l2(u, ou) < 1e-5 and rel_l2(rho, orho) < 1e-5
+        else:
+            assert torch.equal(st, ref), (W, nyb, nzb)
+
+
+def test_invalid_tiling_rejected():
+    case = _fast_case(64, (37, 29), ("x", "y", "z"), (0, 0, 0))
+    sim = make_sim(case, "fp32")
+    for bad in ((5, 5, 5), (4, 2, 5), (8, 0, 1), (8, 5, 28)):
+        with pytest.raises(MaclabError) as ei:
+            sim.set_tiling(*bad)
+        assert ei.value.code == _lib.EINVAL
+    gen = make_sim(workloads.cavity_3d(n=20, Re=10.0), "fp32")
+    assert gen.tiling()["kernel"] == "general"
+    with pytest.raises(MaclabError) as ei:
+        gen.set_tiling(8, 3, 3)
+    assert ei.value.code == _lib.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("precision", ["fp32", "s16", "fp64"])
+def test_autotune_does_not_advance_state(precision):
+    case = _fast_case(128, (20, 30), ("x", "y", "z"), (0, 0, 0))
+    a = make_sim(case, precision)
+    a.step(3)
+    before = a.save_state().clone()
+    ms = a.autotune(reps=3)
+    assert ms > 0
+    assert torch.equal(a.save_state(), before)
+    assert a.params()["steps"] == 3
+    a.step(4)
+    b = make_sim(case, precision)
+    b.step(7)
+    if precision == "fp32":
+        assert torch.equal(a.save_state(), b.save_state())
