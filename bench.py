@@ -130,7 +130,7 @@ def main(argv=None):
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="use the default tiling")
-    ap.add_argument("--tiling", default="", help="W,nyb,nzb of the fast kernel (skips autotuning)")
+    ap.add_argument("--tiling", default="", help="W,nyb,nzb,pf[,kernel] of the fast kernel (skips autotuning)")
     ap.add_argument("--profile-copy-mib", type=int, default=0,
                     help="after timing, run one torch copy of this many MiB (counter calibration)")
     args = ap.parse_args(argv)
@@ -149,7 +149,10 @@ def main(argv=None):
     case = make_case(wl)
     lu = updated_nodes(case)
     d = case.d
-    tiling = tuple(int(v) for v in args.tiling.split(",")) if args.tiling else None
+    tiling = None
+    if args.tiling:
+        parts = args.tiling.split(",")
+        tiling = tuple(int(v) for v in parts[:4]) + ((parts[4],) if len(parts) > 4 else ())
     ms, wall, info = time_variant(case, args.precision, args.steps, args.warmup, not args.no_autotune, tiling)
     diag = info["diag"]
     mlups = lu / (ms * 1e-3) / 1e6

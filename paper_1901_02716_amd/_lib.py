@@ -73,7 +73,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.maclab_save_state.argtypes = [H, ctypes.c_void_p]
     lib.maclab_load_state.argtypes = [H, ctypes.c_void_p]
     lib.maclab_get_tiling.argtypes = [H, ctypes.POINTER(ctypes.c_int)]
-    lib.maclab_set_tiling.argtypes = [H, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.maclab_set_tiling.argtypes = [H, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.maclab_autotune.argtypes = [H, ctypes.c_int, dp]
     lib.maclab_destroy.restype = None
     lib.maclab_destroy.argtypes = [H]

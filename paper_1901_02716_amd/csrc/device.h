@@ -45,7 +45,8 @@ struct StepParams {
   double rho_ref;       // density the stored deviation refers to
   double g[3];          // dt * G / e
   uint64_t seed;        // S16 stochastic rounding
-  uint64_t step;        // index of the step being computed (S16 rounding key)
+  uint64_t step;        // index of the step being computed
+  uint32_t sr_key;      // sr_key(seed, step): rounding key of this step
 };
 
 // --------------------------------------------------------- storage codecs
@@ -53,13 +54,6 @@ struct StepParams {
 // 0 is the density deviation rho - rho_ref, fields 1..D are u~.
 __device__ __forceinline__ uint32_t f32_bits(float v) { return __float_as_uint(v); }
 __device__ __forceinline__ float bits_f32(uint32_t b) { return __uint_as_float(b); }
-
-// Round-to-nearest-even float32 -> bfloat16 bits (NaN stays NaN).
-__device__ __forceinline__ uint32_t bf16_rne(float v) {
-  uint32_t b = f32_bits(v);
-  if ((b & 0x7f800000u) == 0x7f800000u) return (b >> 16) | ((b & 0xffffu) ? 0x40u : 0u);
-  return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
-}
 
 struct CodecF64 {
   using elem = double;
@@ -77,7 +71,8 @@ struct CodecF32 {
   __device__ static elem enc(T v, int, uint32_t) { return v; }
 };
 
-// Split bfloat16: hi = bf16(v), lo = bf16(v - hi), packed as (hi << 16) | lo.
+// Split bfloat16: hi = bf16(v), lo = bf16(v - hi), packed as (hi << 16) | lo
+// (gfx950 converts with v_cvt_pk_bf16_f32, round to nearest even).
 struct CodecHILO {
   using elem = uint32_t;
   using T = float;
@@ -86,18 +81,21 @@ struct CodecHILO {
     return bits_f32(s & 0xffff0000u) + bits_f32(s << 16);
   }
   __device__ static elem enc(T v, int, uint32_t) {
-    uint32_t hi = bf16_rne(v);
-    float rest = v - bits_f32(hi << 16);
-    return (hi << 16) | bf16_rne(rest);
+    const __bf16 hi = (__bf16)v;
+    const __bf16 lo = (__bf16)(v - (float)hi);
+    return ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16) | (uint32_t)__builtin_bit_cast(uint16_t, lo);
   }
 };
 
 // Scaled binary16 with stochastic rounding: the value times 2^10 (density
 // deviation) or 2^6 (velocity) is rounded to one of its two neighbouring
-// binary16 values with probability proportional to proximity. `rnd` supplies
-// 13 uniform bits: they are added below the 10-bit binary16 mantissa of the
-// float32 value, which is then truncated, so the conversion is exact for
-// results in the binary16 normal range (smaller magnitudes round to nearest).
+// binary16 values with probability proportional to proximity. `node_bits`
+// holds one random byte per field (field f uses byte f): the byte is added
+// just below the 10-bit binary16 mantissa of the float32 value (bits 5..12 of
+// the 13 that binary16 drops), which is then truncated, so the conversion is
+// exact for results in the binary16 normal range and rounds up with
+// probability (dropped fraction) to within 2^-8 (smaller magnitudes round to
+// nearest). node_bits = 0x80808080 rounds every field to nearest.
 struct CodecS16 {
   using elem = uint16_t;
   using T = float;
@@ -108,18 +106,22 @@ struct CodecS16 {
     _Float16 h = __builtin_bit_cast(_Float16, s);
     return (float)h * inv_scale(field);
   }
-  __device__ static elem enc(T v, int field, uint32_t rnd) {
+  __device__ static elem enc(T v, int field, uint32_t node_bits) {
     float x = v * scale(field);
     uint32_t b = f32_bits(x);
-    if ((b & 0x7f800000u) != 0x7f800000u) b = (b + (rnd & 0x1fffu)) & ~0x1fffu;
+    const uint32_t r = ((node_bits >> (8 * field)) & 0xffu) << 5;
+    if ((b & 0x7f800000u) != 0x7f800000u) b = (b + r) & ~0x1fffu;
     _Float16 h = (_Float16)bits_f32(b);
     return __builtin_bit_cast(uint16_t, h);
   }
 };
 
-// Counter-based hash (a 32-bit integer finaliser applied to a combination of
-// seed, step, node and field) giving the rounding bits of CodecS16.
-__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+constexpr uint32_t kRoundNearestBits = 0x80808080u;
+
+// Counter-based random bits for CodecS16: a 32-bit integer finaliser of a
+// Weyl sequence over the node index, offset by a key that mixes the seed and
+// the step (computed once per launch on the host).
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
   x ^= x >> 15;
@@ -128,9 +130,12 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   return x;
 }
 
-__device__ __forceinline__ uint32_t sr_bits(uint64_t seed, uint64_t step, int64_t node, int field) {
-  uint32_t h = mix32((uint32_t)seed ^ mix32((uint32_t)(seed >> 32) + (uint32_t)step * 0x9e3779b9u));
-  return mix32(h ^ mix32((uint32_t)node * 4u + (uint32_t)field + (uint32_t)(node >> 30)));
+__host__ __device__ __forceinline__ uint32_t sr_key(uint64_t seed, uint64_t step) {
+  return mix32((uint32_t)seed ^ mix32((uint32_t)(seed >> 32) + (uint32_t)step * 0x9e3779b9u));
+}
+
+__device__ __forceinline__ uint32_t sr_node_bits(uint32_t key, int64_t node) {
+  return mix32((uint32_t)node * 0x9e3779b1u + key);
 }
 
 template <class C>

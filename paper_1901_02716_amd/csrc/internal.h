@@ -47,10 +47,16 @@ hipError_t launch_diagnostics(const Layout& L, const void* state, double rho_ref
                               double* result, hipStream_t s);
 
 // Fast D3Q19 path (kernels_fast.hip). `supported` tells whether the fast
-// kernel handles the layout; a FastShape is its tiling: W output rows per
-// workgroup (one wavefront each), nyb x nzb workgroups with balanced ranges.
+// kernels handle the layout; a FastShape selects one and its tiling.
+// kind 0 (LDS exchange): W output rows per workgroup (one wavefront each,
+// plus two halo rows), nyb x nzb workgroups with balanced ranges, pf source
+// planes loaded ahead. kind 1 (independent wavefronts): W wavefronts per
+// workgroup, each owning one row and one of nzb balanced z-chunks (nyb = 1,
+// pf = 1).
 struct FastShape {
   int W = 8, nyb = 1, nzb = 1;
+  int pf = 1;
+  int kind = 0;
 };
 bool fast_step_supported(const Layout& L, const StepParams& p);
 bool fast_shape_valid(const Layout& L, const StepParams& p, const FastShape& sh);

@@ -31,7 +31,7 @@ struct Fast3DParams {
   int nyb, nzb, nblocks;   // workgroups along y and z, total
   int64_t plane;           // elements per field plane
   float rho_ref, gx, gy, gz;
-  uint64_t seed, step;
+  uint32_t sr_key;         // S16 rounding key of this step
 };
 
 // ----------------------------------------------------------- row load/store
@@ -47,21 +47,14 @@ __device__ __forceinline__ void load_row(const typename C::elem* __restrict__ p,
   for (int e = 0; e < KX; ++e) out[e] = (float)C::dec(r.v[e], field);
 }
 
-template <class C, int KX>
-__device__ __forceinline__ typename C::elem enc_one(float v, int field, int64_t node, const Fast3DParams& p) {
-  uint32_t r = 0;
-  if constexpr (needs_rng<C>::value) r = sr_bits(p.seed, p.step, node, field);
-  return C::enc(v, field, r);
-}
-
 // Stores one row of one field; with x walls the first node of lane 0 and the
 // last node of lane 63 (the wall nodes) are left untouched.
 template <class C, int KX>
 __device__ __forceinline__ void store_row(typename C::elem* __restrict__ p, int field, const float (&v)[KX],
-                                          int64_t node0, int lane, bool xwall, const Fast3DParams& pr) {
+                                          const uint32_t (&bits)[KX], int lane, bool xwall) {
   RowVec<C, KX> r;
 #pragma unroll
-  for (int e = 0; e < KX; ++e) r.v[e] = enc_one<C, KX>(v[e], field, node0 + e, pr);
+  for (int e = 0; e < KX; ++e) r.v[e] = C::enc(v[e], field, bits[e]);
   if (xwall && (lane == 0 || lane == 63)) {
 #pragma unroll
     for (int e = 0; e < KX; ++e) {
@@ -103,137 +96,191 @@ struct PlaneAcc {
   }
 };
 
-// Pushes one source row (the KX nodes of this lane) into the three plane
-// accumulators of this wavefront and into this wavefront's LDS rows.
-// acc_m: destination plane z-1, acc_c: plane z, acc_p: plane z+1.
-// MODE 0: an output row (everything); MODE 1: the halo row below the tile
-// (only its c_y = +1 links are needed); MODE 2: the halo row above (c_y = -1).
-// Floating-point contraction is off and every FMA is written out, so a link
-// value has the same bits whichever wavefront (output or halo) computes it,
-// and the result does not depend on the tiling.
+// The 19 link values of one node, times 36, in deviation form (Eq. (2)):
+//   36 F^_a = wnum_a [a + c.b + sum_i c_i^2 q_ii + sum_{i<j} c_i c_j q_ij]
+// with a = drho - 1.5 rho |u|^2, b = 3 rho u, q_ii = 4.5 rho u_i^2,
+// q_ij = 9 rho u_i u_j. The six axis links are carried halved (h = F/2).
+struct Links {
+  float f0, hxp, hxm, hyp, hym, hzp, hzm;
+  float pp0, mm0, pm0, mp0;  // (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0)
+  float p0p, m0m, p0m, m0p;  // (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1)
+  float zpp, zmm, zpm, zmp;  // (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1)
+};
+
+// Contraction is off and every FMA is written out, so a link value has the
+// same bits whichever wavefront (output or halo row) computes it and the
+// result does not depend on the tiling.
+__device__ __forceinline__ void node_links(float dr, float ux, float uy, float uz, float rho_ref, Links& L) {
+#pragma clang fp contract(off)
+  const float rho = rho_ref + dr;
+  const float r3 = 3.f * rho;
+  const float bx = r3 * ux, by = r3 * uy, bz = r3 * uz;    // 3 rho u
+  const float cxx = bx * ux, cyy = by * uy, czz = bz * uz;  // 3 rho u_i^2  (q_ii = 1.5 c_ii)
+  const float cxy = bx * uy, cxz = bx * uz, cyz = by * uz;  // 3 rho u_i u_j (q_ij = 3 c_ij)
+  const float a = __builtin_fmaf((cxx + cyy) + czz, -0.5f, dr);
+  const float sx = __builtin_fmaf(cxx, 1.5f, a), sy = __builtin_fmaf(cyy, 1.5f, a), sz = __builtin_fmaf(czz, 1.5f, a);
+  L.f0 = 12.f * a;
+  L.hxp = sx + bx;
+  L.hxm = sx - bx;
+  L.hyp = sy + by;
+  L.hym = sy - by;
+  L.hzp = sz + bz;
+  L.hzm = sz - bz;
+  float t, p, m, u, v;
+  t = __builtin_fmaf(cyy, 1.5f, sx);  // a + q_xx + q_yy
+  p = __builtin_fmaf(cxy, 3.f, t);
+  m = __builtin_fmaf(cxy, -3.f, t);
+  u = bx + by;
+  v = bx - by;
+  L.pp0 = p + u;
+  L.mm0 = p - u;
+  L.pm0 = m + v;
+  L.mp0 = m - v;
+  t = __builtin_fmaf(czz, 1.5f, sx);  // a + q_xx + q_zz
+  p = __builtin_fmaf(cxz, 3.f, t);
+  m = __builtin_fmaf(cxz, -3.f, t);
+  u = bx + bz;
+  v = bx - bz;
+  L.p0p = p + u;
+  L.m0m = p - u;
+  L.p0m = m + v;
+  L.m0p = m - v;
+  t = __builtin_fmaf(czz, 1.5f, sy);  // a + q_yy + q_zz
+  p = __builtin_fmaf(cyz, 3.f, t);
+  m = __builtin_fmaf(cyz, -3.f, t);
+  u = by + bz;
+  v = by - bz;
+  L.zpp = p + u;
+  L.zmm = p - u;
+  L.zpm = m + v;
+  L.zmp = m - v;
+}
+
+// Pushes one source row (the KX nodes of this lane).
+// MODE 0 (output row): c_y = 0 links go into the plane accumulators of this
+// wavefront -- am (destination plane z-1), ac (plane z), ap (plane z+1, which
+// this call is the first to touch, so it is assigned) -- and c_y = +-1 links
+// into this wavefront's LDS rows. MODE 1 / 2 (halo row below / above the
+// tile): only the c_y = +1 / -1 links, to LDS.
+template <int KX>
+__device__ __forceinline__ void own_row_links(const float (&f0)[KX], const float (&hzp)[KX], const float (&hzm)[KX],
+                                              const float (&hxp)[KX], const float (&p0p)[KX], const float (&p0m)[KX],
+                                              const float (&hxm)[KX], const float (&m0p)[KX], const float (&m0m)[KX],
+                                              PlaneAcc<KX>& am, PlaneAcc<KX>& ac, PlaneAcc<KX>& ap);
+
 template <int KX, int MODE>
 __device__ __forceinline__ void push_row(const float (&dr)[KX], const float (&ux)[KX], const float (&uy)[KX],
-                                         const float (&uz)[KX], float rho_ref, PlaneAcc<KX>& acc_m,
-                                         PlaneAcc<KX>& acc_c, PlaneAcc<KX>& acc_p, float* __restrict__ up,
+                                         const float (&uz)[KX], float rho_ref, PlaneAcc<KX>& am,
+                                         PlaneAcc<KX>& ac, PlaneAcc<KX>& ap, float* __restrict__ up,
                                          float* __restrict__ dn, int lane) {
 #pragma clang fp contract(off)
   constexpr int NX = 64 * KX;
-  // values leaving the lane through its right / left edge (axis links are
-  // carried as halves: the link value is twice the carried number)
-  float out_r0 = 0.f, out_r1 = 0.f, out_r2 = 0.f;  // (1,0,0)/2, (1,0,1), (1,0,-1) of the last node
-  float out_l0 = 0.f, out_l1 = 0.f, out_l2 = 0.f;  // (-1,0,0)/2, (-1,0,1), (-1,0,-1) of the first node
+  // c_y = 0 links kept per node: rest, +-z, and the four links that move in x
+  float f0[KX], hzp[KX], hzm[KX];
+  float hxp[KX], p0p[KX], p0m[KX];  // move to x+1
+  float hxm[KX], m0p[KX], m0m[KX];  // move to x-1
 #pragma unroll
   for (int e = 0; e < KX; ++e) {
-    // equilibria of the 19 links, times 36, in deviation form (Eq. (2)):
-    // 36 F^_a = wnum_a [a + c.b + sum_i c_i^2 q_ii + sum_{i<j} c_i c_j q_ij]
-    const float rho = rho_ref + dr[e];
-    const float tx = 3.f * ux[e], ty = 3.f * uy[e], tz = 3.f * uz[e];
-    const float bx = rho * tx, by = rho * ty, bz = rho * tz;                      // 3 rho u
-    const float qxx = bx * (1.5f * ux[e]), qyy = by * (1.5f * uy[e]), qzz = bz * (1.5f * uz[e]);  // 4.5 rho u_i^2
-    const float qxy = bx * ty, qxz = bx * tz, qyz = by * tz;                      // 9 rho u_i u_j
-    const float a = __builtin_fmaf(qxx + qyy + qzz, -1.f / 3.f, dr[e]);           // drho - 1.5 rho |u|^2
-    const float sx = a + qxx, sy = a + qyy, sz = a + qzz;
-    const float f0 = 12.f * a;
-    // axis links, halved: 36 F^ = 2 (s_i +- b_i)
-    const float hxp = sx + bx, hxm = sx - bx;
-    const float hyp = sy + by, hym = sy - by;
-    const float hzp = sz + bz, hzm = sz - bz;
-    float p, m, u, v;
-    // xy edges
-    p = (sx + qyy) + qxy; m = (sx + qyy) - qxy; u = bx + by; v = bx - by;
-    const float f_pp0 = p + u, f_mm0 = p - u, f_pm0 = m + v, f_mp0 = m - v;
-    // xz edges
-    p = (sx + qzz) + qxz; m = (sx + qzz) - qxz; u = bx + bz; v = bx - bz;
-    const float f_p0p = p + u, f_m0m = p - u, f_p0m = m + v, f_m0p = m - v;
-    // yz edges
-    p = (sy + qzz) + qyz; m = (sy + qzz) - qyz; u = by + bz; v = by - bz;
-    const float f_0pp = p + u, f_0mm = p - u, f_0pm = m + v, f_0mp = m - v;
-
-    if constexpr (MODE == 0) {
-      // c_y = 0 links: plane z (rest, +-x), plane z+1 (+z, +-x+z), plane z-1
-      acc_c.r[e] += f0;
-      acc_p.r[e] = __builtin_fmaf(2.f, hzp, acc_p.r[e]);
-      acc_p.mz[e] = __builtin_fmaf(2.f, hzp, acc_p.mz[e]);
-      acc_m.r[e] = __builtin_fmaf(2.f, hzm, acc_m.r[e]);
-      acc_m.mz[e] = __builtin_fmaf(-2.f, hzm, acc_m.mz[e]);
-      if (e + 1 < KX) {
-        acc_c.r[e + 1] = __builtin_fmaf(2.f, hxp, acc_c.r[e + 1]);
-        acc_c.mx[e + 1] = __builtin_fmaf(2.f, hxp, acc_c.mx[e + 1]);
-        acc_p.r[e + 1] += f_p0p;
-        acc_p.mx[e + 1] += f_p0p;
-        acc_p.mz[e + 1] += f_p0p;
-        acc_m.r[e + 1] += f_p0m;
-        acc_m.mx[e + 1] += f_p0m;
-        acc_m.mz[e + 1] -= f_p0m;
-      } else {
-        out_r0 = hxp;
-        out_r1 = f_p0p;
-        out_r2 = f_p0m;
-      }
-      if (e > 0) {
-        acc_c.r[e - 1] = __builtin_fmaf(2.f, hxm, acc_c.r[e - 1]);
-        acc_c.mx[e - 1] = __builtin_fmaf(-2.f, hxm, acc_c.mx[e - 1]);
-        acc_p.r[e - 1] += f_m0p;
-        acc_p.mx[e - 1] -= f_m0p;
-        acc_p.mz[e - 1] += f_m0p;
-        acc_m.r[e - 1] += f_m0m;
-        acc_m.mx[e - 1] -= f_m0m;
-        acc_m.mz[e - 1] -= f_m0m;
-      } else {
-        out_l0 = hxm;
-        out_l1 = f_m0p;
-        out_l2 = f_m0m;
-      }
-    }
-    // c_y = +1 links to the next row, c_y = -1 links to the previous row
-    // (the axis link halved); LDS rows are stored transposed (node KX*l + e
-    // at e*64 + l) so that a wavefront touches 64 consecutive words
+    Links L;
+    node_links(dr[e], ux[e], uy[e], uz[e], rho_ref, L);
+    // c_y = +1 links to the next row, c_y = -1 links to the previous row;
+    // LDS rows are stored transposed (node KX*l + e at e*64 + l) so that a
+    // wavefront touches 64 consecutive words
     const int x = e * 64 + lane;
     if constexpr (MODE != 2) {
-      up[0 * NX + x] = hyp;
-      up[1 * NX + x] = f_pp0;
-      up[2 * NX + x] = f_mp0;
-      up[3 * NX + x] = f_0pp;
-      up[4 * NX + x] = f_0pm;
+      up[0 * NX + x] = L.hyp;
+      up[1 * NX + x] = L.pp0;
+      up[2 * NX + x] = L.mp0;
+      up[3 * NX + x] = L.zpp;
+      up[4 * NX + x] = L.zpm;
     }
     if constexpr (MODE != 1) {
-      dn[0 * NX + x] = hym;
-      dn[1 * NX + x] = f_pm0;
-      dn[2 * NX + x] = f_mm0;
-      dn[3 * NX + x] = f_0mp;
-      dn[4 * NX + x] = f_0mm;
+      dn[0 * NX + x] = L.hym;
+      dn[1 * NX + x] = L.pm0;
+      dn[2 * NX + x] = L.mm0;
+      dn[3 * NX + x] = L.zmp;
+      dn[4 * NX + x] = L.zmm;
     }
+    f0[e] = L.f0;
+    hzp[e] = L.hzp;
+    hzm[e] = L.hzm;
+    hxp[e] = L.hxp;
+    p0p[e] = L.p0p;
+    p0m[e] = L.p0m;
+    hxm[e] = L.hxm;
+    m0p[e] = L.m0p;
+    m0m[e] = L.m0m;
   }
-  if constexpr (MODE != 0) return;
-  // cross-lane x shifts: the last node's +x links enter the next lane's first
-  // node, the first node's -x links enter the previous lane's last node
-  const float in_r0 = from_left_lane(out_r0), in_r1 = from_left_lane(out_r1), in_r2 = from_left_lane(out_r2);
-  const float in_l0 = from_right_lane(out_l0), in_l1 = from_right_lane(out_l1), in_l2 = from_right_lane(out_l2);
-  acc_c.r[0] = __builtin_fmaf(2.f, in_r0, acc_c.r[0]);
-  acc_c.mx[0] = __builtin_fmaf(2.f, in_r0, acc_c.mx[0]);
-  acc_p.r[0] += in_r1;
-  acc_p.mx[0] += in_r1;
-  acc_p.mz[0] += in_r1;
-  acc_m.r[0] += in_r2;
-  acc_m.mx[0] += in_r2;
-  acc_m.mz[0] -= in_r2;
-  acc_c.r[KX - 1] = __builtin_fmaf(2.f, in_l0, acc_c.r[KX - 1]);
-  acc_c.mx[KX - 1] = __builtin_fmaf(-2.f, in_l0, acc_c.mx[KX - 1]);
-  acc_p.r[KX - 1] += in_l1;
-  acc_p.mx[KX - 1] -= in_l1;
-  acc_p.mz[KX - 1] += in_l1;
-  acc_m.r[KX - 1] += in_l2;
-  acc_m.mx[KX - 1] -= in_l2;
-  acc_m.mz[KX - 1] -= in_l2;
+  if constexpr (MODE == 0) own_row_links<KX>(f0, hzp, hzm, hxp, p0p, p0m, hxm, m0p, m0m, am, ac, ap);
 }
 
-// Adds the c_y = +-1 links arriving from the rows below (`from_below`, sent
-// with c_y = +1) and above (`from_above`, c_y = -1).
+// The c_y = 0 links of a row into the plane accumulators: rest, +-z, and the
+// links moving in x, which cross to the neighbouring lane at the lane edges.
+// Plane z+1 (ap) is first touched here, so it is assigned.
+template <int KX>
+__device__ __forceinline__ void own_row_links(const float (&f0)[KX], const float (&hzp)[KX], const float (&hzm)[KX],
+                                              const float (&hxp)[KX], const float (&p0p)[KX], const float (&p0m)[KX],
+                                              const float (&hxm)[KX], const float (&m0p)[KX], const float (&m0m)[KX],
+                                              PlaneAcc<KX>& am, PlaneAcc<KX>& ac, PlaneAcc<KX>& ap) {
+#pragma clang fp contract(off)
+  const float in_hxp = from_left_lane(hxp[KX - 1]), in_p0p = from_left_lane(p0p[KX - 1]),
+              in_p0m = from_left_lane(p0m[KX - 1]);
+  const float in_hxm = from_right_lane(hxm[0]), in_m0p = from_right_lane(m0p[0]), in_m0m = from_right_lane(m0m[0]);
+#pragma unroll
+  for (int d = 0; d < KX; ++d) {
+    // links arriving at node d from d-1 (moving +x) and d+1 (moving -x)
+    const float Phx = d > 0 ? hxp[d - 1] : in_hxp, Pzp = d > 0 ? p0p[d - 1] : in_p0p,
+                Pzm = d > 0 ? p0m[d - 1] : in_p0m;
+    const float Mhx = d < KX - 1 ? hxm[d + 1] : in_hxm, Mzp = d < KX - 1 ? m0p[d + 1] : in_m0p,
+                Mzm = d < KX - 1 ? m0m[d + 1] : in_m0m;
+    // plane z: rest and +-x
+    const float A = Phx + Mhx, B = Phx - Mhx;
+    ac.r[d] += __builtin_fmaf(2.f, A, f0[d]);
+    ac.mx[d] = __builtin_fmaf(2.f, B, ac.mx[d]);
+    // plane z+1: +z, +x+z, -x+z (first contributions to this plane)
+    const float sp = __builtin_fmaf(2.f, hzp[d], Pzp + Mzp);
+    ap.r[d] = sp;
+    ap.mz[d] = sp;
+    ap.mx[d] = Pzp - Mzp;
+    // plane z-1: -z, +x-z, -x-z
+    const float sm = __builtin_fmaf(2.f, hzm[d], Pzm + Mzm);
+    am.r[d] += sm;
+    am.mz[d] -= sm;
+    am.mx[d] += Pzm - Mzm;
+  }
+}
+
+// Adds the c_y = +1 links arriving from the row below (S = +1) or the c_y =
+// -1 links from the row above (S = -1) to the plane accumulators. For node d
+// the arriving links are h (the axis link, halved), ep from node d-1 (moving
+// +x), em from node d+1 (moving -x), and vp / vm (moving +z / -z). The y
+// momentum of plane z+1 is first touched by the row below, so it is assigned.
+template <int KX, int S>
+__device__ __forceinline__ void add_row_links(float h, float ep_from_left, float em_from_right, float vp, float vm,
+                                              int d, PlaneAcc<KX>& am, PlaneAcc<KX>& ac, PlaneAcc<KX>& ap) {
+#pragma clang fp contract(off)
+  const float s = __builtin_fmaf(2.f, h, ep_from_left + em_from_right);
+  ac.r[d] += s;
+  ac.mx[d] += ep_from_left - em_from_right;
+  ap.r[d] += vp;
+  ap.mz[d] += vp;
+  am.r[d] += vm;
+  am.mz[d] -= vm;
+  if constexpr (S > 0) {
+    ac.my[d] += s;
+    ap.my[d] = vp;
+    am.my[d] += vm;
+  } else {
+    ac.my[d] -= s;
+    ap.my[d] -= vp;
+    am.my[d] -= vm;
+  }
+}
+
+// Adds the links sent through LDS by the rows below and above.
 template <int KX>
 __device__ __forceinline__ void pull_rows(const float* __restrict__ from_below, const float* __restrict__ from_above,
-                                          PlaneAcc<KX>& acc_m, PlaneAcc<KX>& acc_c, PlaneAcc<KX>& acc_p,
-                                          int lane) {
-#pragma clang fp contract(off)
+                                          PlaneAcc<KX>& am, PlaneAcc<KX>& ac, PlaneAcc<KX>& ap, int lane) {
   constexpr int NX = 64 * KX;
 #pragma unroll
   for (int e = 0; e < KX; ++e) {
@@ -241,25 +288,20 @@ __device__ __forceinline__ void pull_rows(const float* __restrict__ from_below, 
     const int x = e * 64 + lane;
     const int xl = e > 0 ? (e - 1) * 64 + lane : (KX - 1) * 64 + ((lane + 63) & 63);
     const int xr = e < KX - 1 ? (e + 1) * 64 + lane : ((lane + 1) & 63);
-    const float a0 = from_below[0 * NX + x], a1 = from_below[1 * NX + xl], a2 = from_below[2 * NX + xr];
-    const float a3 = from_below[3 * NX + x], a4 = from_below[4 * NX + x];
-    const float b0 = from_above[0 * NX + x], b1 = from_above[1 * NX + xl], b2 = from_above[2 * NX + xr];
-    const float b3 = from_above[3 * NX + x], b4 = from_above[4 * NX + x];
-    const float sa = __builtin_fmaf(2.f, a0, a1 + a2), sb = __builtin_fmaf(2.f, b0, b1 + b2);
-    acc_c.r[e] += sa + sb;
-    acc_c.my[e] += sa - sb;
-    acc_c.mx[e] += (a1 - a2) + (b1 - b2);
-    const float s3 = a3 + b3, s4 = a4 + b4;
-    acc_p.r[e] += s3;
-    acc_p.mz[e] += s3;
-    acc_p.my[e] += a3 - b3;
-    acc_m.r[e] += s4;
-    acc_m.mz[e] -= s4;
-    acc_m.my[e] += a4 - b4;
+    add_row_links<KX, 1>(from_below[0 * NX + x], from_below[1 * NX + xl], from_below[2 * NX + xr],
+                         from_below[3 * NX + x], from_below[4 * NX + x], e, am, ac, ap);
+    add_row_links<KX, -1>(from_above[0 * NX + x], from_above[1 * NX + xl], from_above[2 * NX + xr],
+                          from_above[3 * NX + x], from_above[4 * NX + x], e, am, ac, ap);
   }
 }
 
-template <class C, int KX, int W>
+template <int KX>
+struct RowData {
+  float dr[KX], ux[KX], uy[KX], uz[KX];
+};
+
+// PF: source planes loaded ahead (1 or 2).
+template <class C, int KX, int W, int PF>
 __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C::elem* __restrict__ src,
                                                                typename C::elem* __restrict__ dst, Fast3DParams p) {
   constexpr int NX = 64 * KX;
@@ -271,7 +313,6 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
   float* dn = lds + (ROWS + wv) * 5 * NX;      // this wave's c_y = -1 links
   const float* from_below = lds + (wv > 0 ? wv - 1 : 0) * 5 * NX;
   const float* from_above = lds + (ROWS + (wv + 1 < ROWS ? wv + 1 : wv)) * 5 * NX;
-  (void)W;
 
   // XCD-aware tile numbering: XCD k (= blockIdx.x mod 8) gets a contiguous band
   const int bid = blockIdx.x;
@@ -298,27 +339,27 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
   const int64_t nx = NX;
   const int64_t plane = p.plane;
 
-  float dr[KX], ux[KX], uy[KX], uz[KX];
   auto zwrap = [&](int z) { return p.zper ? (z + p.nz) % p.nz : z; };
-  auto load_plane = [&](int z) {
+  auto load_plane = [&](int z, RowData<KX>& b) {
     const int64_t base = nx * ((int64_t)yrow + (int64_t)p.ny * zwrap(z)) + xbase;
-    load_row<C, KX>(src + base, 0, dr);
-    load_row<C, KX>(src + plane + base, 1, ux);
-    load_row<C, KX>(src + 2 * plane + base, 2, uy);
-    load_row<C, KX>(src + 3 * plane + base, 3, uz);
+    load_row<C, KX>(src + base, 0, b.dr);
+    load_row<C, KX>(src + plane + base, 1, b.ux);
+    load_row<C, KX>(src + 2 * plane + base, 2, b.uy);
+    load_row<C, KX>(src + 3 * plane + base, 3, b.uz);
   };
 
   // One source plane: push its links, exchange the c_y = +-1 links through
   // LDS, then finalise destination plane zs-1. am / ac / ap are the
-  // accumulators of destination planes zs-1, zs, zs+1.
-  auto source_plane = [&](int zs, PlaneAcc<KX>& am, PlaneAcc<KX>& ac, PlaneAcc<KX>& ap) {
+  // accumulators of destination planes zs-1, zs, zs+1; b holds plane zs and
+  // is refilled with plane zs+PF.
+  auto source_plane = [&](int zs, PlaneAcc<KX>& am, PlaneAcc<KX>& ac, PlaneAcc<KX>& ap, RowData<KX>& b) {
     if (mode == 0)
-      push_row<KX, 0>(dr, ux, uy, uz, p.rho_ref, am, ac, ap, up, dn, lane);
+      push_row<KX, 0>(b.dr, b.ux, b.uy, b.uz, p.rho_ref, am, ac, ap, up, dn, lane);
     else if (mode == 1)
-      push_row<KX, 1>(dr, ux, uy, uz, p.rho_ref, am, ac, ap, up, dn, lane);
+      push_row<KX, 1>(b.dr, b.ux, b.uy, b.uz, p.rho_ref, am, ac, ap, up, dn, lane);
     else if (mode == 2)
-      push_row<KX, 2>(dr, ux, uy, uz, p.rho_ref, am, ac, ap, up, dn, lane);
-    if (zs < z1 && mode != 3) load_plane(zs + 1);  // prefetch the next source plane
+      push_row<KX, 2>(b.dr, b.ux, b.uy, b.uz, p.rho_ref, am, ac, ap, up, dn, lane);
+    if (zs + PF <= z1 && mode != 3) load_plane(zs + PF, b);
     __syncthreads();
     if (out_row) pull_rows<KX>(from_below, from_above, am, ac, ap, lane);
     __syncthreads();
@@ -335,21 +376,166 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
         vz[e] = __builtin_fmaf(am.mz[e], 1.f / 36.f, p.gz) * inv;
       }
       const int64_t node0 = nx * ((int64_t)yrow + (int64_t)p.ny * zwrap(zd)) + xbase;
-      store_row<C, KX>(dst + node0, 0, r, node0, lane, p.xwall, p);
-      store_row<C, KX>(dst + plane + node0, 1, vx, node0, lane, p.xwall, p);
-      store_row<C, KX>(dst + 2 * plane + node0, 2, vy, node0, lane, p.xwall, p);
-      store_row<C, KX>(dst + 3 * plane + node0, 3, vz, node0, lane, p.xwall, p);
+      uint32_t bits[KX];
+#pragma unroll
+      for (int e = 0; e < KX; ++e) bits[e] = needs_rng<C>::value ? sr_node_bits(p.sr_key, node0 + e) : 0u;
+      store_row<C, KX>(dst + node0, 0, r, bits, lane, p.xwall);
+      store_row<C, KX>(dst + plane + node0, 1, vx, bits, lane, p.xwall);
+      store_row<C, KX>(dst + 2 * plane + node0, 2, vy, bits, lane, p.xwall);
+      store_row<C, KX>(dst + 3 * plane + node0, 3, vz, bits, lane, p.xwall);
     }
-    am.zero();  // becomes destination plane zs+2
   };
 
-  // source planes z0-1 .. z1, three at a time so the accumulator roles
-  // rotate at compile time
+  // source planes z0-1 .. z1; six per trip so that the accumulator roles
+  // (period 3) and the prefetch buffers (period PF) rotate at compile time.
+  // The destination planes z0-2 and z0-1 start from zero; plane zs+1 is
+  // assigned by the push of plane zs.
   PlaneAcc<KX> a0, a1, a2;
   a0.zero();
   a1.zero();
-  a2.zero();
-  if (mode != 3) load_plane(z0 - 1);
+  RowData<KX> b0, b1;
+  if (mode != 3) {
+    load_plane(z0 - 1, b0);
+    if (PF == 2) load_plane(z0, b1);
+  }
+  RowData<KX>& c1 = PF == 2 ? b1 : b0;
+  for (int zs = z0 - 1; zs <= z1; zs += 6) {
+    source_plane(zs, a0, a1, a2, b0);
+    if (zs + 1 > z1) break;
+    source_plane(zs + 1, a1, a2, a0, c1);
+    if (zs + 2 > z1) break;
+    source_plane(zs + 2, a2, a0, a1, b0);
+    if (zs + 3 > z1) break;
+    source_plane(zs + 3, a0, a1, a2, c1);
+    if (zs + 4 > z1) break;
+    source_plane(zs + 4, a1, a2, a0, b0);
+    if (zs + 5 > z1) break;
+    source_plane(zs + 5, a2, a0, a1, c1);
+  }
+}
+
+// ----------------------------------------------- barrier-free variant
+// Each wavefront owns one output x-row and a z-range and works alone, with
+// no LDS and no barriers: per source plane it reads its own row and the rows
+// below and above (the neighbouring rows come from the caches), evaluates the
+// c_y = 0 links of its own row and, of the neighbouring rows, only the links
+// that reach it. Link values and the order of every sum are those of the
+// exchange kernel above, so both kernels give the same bits.
+template <int KX, int S>
+__device__ __forceinline__ void neighbour_row(const RowData<KX>& b, float rho_ref, int d_unused, PlaneAcc<KX>& am,
+                                              PlaneAcc<KX>& ac, PlaneAcc<KX>& ap) {
+  (void)d_unused;
+  float h[KX], ep[KX], em[KX], vp[KX], vm[KX];
+#pragma unroll
+  for (int e = 0; e < KX; ++e) {
+    Links L;
+    node_links(b.dr[e], b.ux[e], b.uy[e], b.uz[e], rho_ref, L);
+    if constexpr (S > 0) {
+      h[e] = L.hyp;
+      ep[e] = L.pp0;
+      em[e] = L.mp0;
+      vp[e] = L.zpp;
+      vm[e] = L.zpm;
+    } else {
+      h[e] = L.hym;
+      ep[e] = L.pm0;
+      em[e] = L.mm0;
+      vp[e] = L.zmp;
+      vm[e] = L.zmm;
+    }
+  }
+  const float in_ep = from_left_lane(ep[KX - 1]);
+  const float in_em = from_right_lane(em[0]);
+#pragma unroll
+  for (int d = 0; d < KX; ++d) {
+    const float epl = d > 0 ? ep[d - 1] : in_ep;
+    const float emr = d < KX - 1 ? em[d + 1] : in_em;
+    add_row_links<KX, S>(h[d], epl, emr, vp[d], vm[d], d, am, ac, ap);
+  }
+}
+
+template <class C, int KX, int NWV>
+__global__ __launch_bounds__(64 * NWV) void step_d3q19_indep(const typename C::elem* __restrict__ src,
+                                                             typename C::elem* __restrict__ dst, Fast3DParams p) {
+  const int lane = threadIdx.x;
+  const int wv = threadIdx.y;
+  const int bid = blockIdx.x;
+  const int per = p.nblocks >> 3, rem = p.nblocks & 7, xcd = bid & 7;
+  const int blk = xcd * per + (xcd < rem ? xcd : rem) + (bid >> 3);
+  const int64_t g = (int64_t)blk * NWV + wv;  // wavefront index: row fastest
+  if (g >= (int64_t)p.nyo * p.nzb) return;
+  const int row = (int)(g % p.nyo), zc = (int)(g / p.nyo);
+  const int y = p.ylo + row;
+  const int z0 = p.zlo + (int)((int64_t)zc * p.nzo / p.nzb);
+  const int z1 = p.zlo + (int)((int64_t)(zc + 1) * p.nzo / p.nzb);
+  auto ywrap = [&](int v) { return p.yper ? (v + p.ny) % p.ny : v; };
+  const int yb = ywrap(y - 1), ya = ywrap(y + 1);
+  const int xbase = lane * KX;
+  constexpr int64_t nx = 64 * KX;
+  const int64_t plane = p.plane;
+  auto zwrap = [&](int z) { return p.zper ? (z + p.nz) % p.nz : z; };
+  auto load = [&](int yy, int z, RowData<KX>& b) {
+    const int64_t base = nx * ((int64_t)yy + (int64_t)p.ny * zwrap(z)) + xbase;
+    load_row<C, KX>(src + base, 0, b.dr);
+    load_row<C, KX>(src + plane + base, 1, b.ux);
+    load_row<C, KX>(src + 2 * plane + base, 2, b.uy);
+    load_row<C, KX>(src + 3 * plane + base, 3, b.uz);
+  };
+
+  RowData<KX> own, below, above;
+  auto source_plane = [&](int zs, PlaneAcc<KX>& am, PlaneAcc<KX>& ac, PlaneAcc<KX>& ap) {
+    {
+      float f0[KX], hzp[KX], hzm[KX], hxp[KX], p0p[KX], p0m[KX], hxm[KX], m0p[KX], m0m[KX];
+#pragma unroll
+      for (int e = 0; e < KX; ++e) {
+        Links L;
+        node_links(own.dr[e], own.ux[e], own.uy[e], own.uz[e], p.rho_ref, L);
+        f0[e] = L.f0;
+        hzp[e] = L.hzp;
+        hzm[e] = L.hzm;
+        hxp[e] = L.hxp;
+        p0p[e] = L.p0p;
+        p0m[e] = L.p0m;
+        hxm[e] = L.hxm;
+        m0p[e] = L.m0p;
+        m0m[e] = L.m0m;
+      }
+      if (zs < z1) load(y, zs + 1, own);
+      own_row_links<KX>(f0, hzp, hzm, hxp, p0p, p0m, hxm, m0p, m0m, am, ac, ap);
+    }
+    neighbour_row<KX, 1>(below, p.rho_ref, 0, am, ac, ap);
+    if (zs < z1) load(yb, zs + 1, below);
+    neighbour_row<KX, -1>(above, p.rho_ref, 0, am, ac, ap);
+    if (zs < z1) load(ya, zs + 1, above);
+    const int zd = zs - 1;
+    if (zd >= z0) {
+      float r[KX], vx[KX], vy[KX], vz[KX];
+#pragma unroll
+      for (int e = 0; e < KX; ++e) {
+        const float drn = am.r[e] * (1.f / 36.f);
+        const float inv = __builtin_amdgcn_rcpf(p.rho_ref + drn);  // v_rcp_f32, 1 ulp
+        r[e] = drn;
+        vx[e] = __builtin_fmaf(am.mx[e], 1.f / 36.f, p.gx) * inv;
+        vy[e] = __builtin_fmaf(am.my[e], 1.f / 36.f, p.gy) * inv;
+        vz[e] = __builtin_fmaf(am.mz[e], 1.f / 36.f, p.gz) * inv;
+      }
+      const int64_t node0 = nx * ((int64_t)y + (int64_t)p.ny * zwrap(zd)) + xbase;
+      uint32_t bits[KX];
+#pragma unroll
+      for (int e = 0; e < KX; ++e) bits[e] = needs_rng<C>::value ? sr_node_bits(p.sr_key, node0 + e) : 0u;
+      store_row<C, KX>(dst + node0, 0, r, bits, lane, p.xwall);
+      store_row<C, KX>(dst + plane + node0, 1, vx, bits, lane, p.xwall);
+      store_row<C, KX>(dst + 2 * plane + node0, 2, vy, bits, lane, p.xwall);
+      store_row<C, KX>(dst + 3 * plane + node0, 3, vz, bits, lane, p.xwall);
+    }
+  };
+
+  PlaneAcc<KX> a0, a1, a2;
+  a0.zero();
+  a1.zero();
+  load(y, z0 - 1, own);
+  load(yb, z0 - 1, below);
+  load(ya, z0 - 1, above);
   for (int zs = z0 - 1; zs <= z1; zs += 3) {
     source_plane(zs, a0, a1, a2);
     if (zs + 1 > z1) break;
@@ -379,9 +565,19 @@ static void output_ranges(const Layout& L, const StepParams& p, int* nyo, int* n
 bool fast_shape_valid(const Layout& L, const StepParams& p, const FastShape& sh) {
   int nyo, nzo;
   output_ranges(L, p, &nyo, &nzo);
+  if (sh.kind == 1) {
+    // the independent kernel keeps three row buffers and three plane
+    // accumulators per lane: it fits the register file only at nx = 64
+    if (L.nx != 64) return false;
+    const bool w_ok = sh.W == 1 || sh.W == 2 || sh.W == 4 || sh.W == 8;
+    return w_ok && sh.nyb == 1 && sh.pf == 1 && sh.nzb >= 1 && sh.nzb <= nzo;
+  }
+  if (sh.kind != 0) return false;
   bool w_ok = false;
   for (int w : kFastW) w_ok |= (w == sh.W);
-  if (!w_ok || sh.nyb < 1 || sh.nzb < 1 || sh.nyb > nyo || sh.nzb > nzo) return false;
+  if (!w_ok || (sh.pf != 1 && sh.pf != 2) || sh.nyb < 1 || sh.nzb < 1 || sh.nyb > nyo || sh.nzb > nzo)
+    return false;
+  if (sh.pf == 2 && sh.W > 10) return false;  // the two-plane buffer would not fit in registers
   return (nyo + sh.nyb - 1) / sh.nyb <= sh.W;
 }
 
@@ -392,6 +588,7 @@ FastShape fast_default_shape(const Layout& L, const StepParams& p, int cus) {
   output_ranges(L, p, &nyo, &nzo);
   FastShape sh;
   sh.W = 8;
+  sh.pf = 1;
   sh.nyb = (nyo + sh.W - 1) / sh.W;
   sh.nzb = cus / sh.nyb;
   if (sh.nzb < 1) sh.nzb = 1;
@@ -403,48 +600,91 @@ int fast_candidates(const Layout& L, const StepParams& p, int cus, FastShape* ou
   int nyo, nzo;
   output_ranges(L, p, &nyo, &nzo);
   int n = 0;
+  // independent wavefronts: about 8, 12, 16 or 24 per CU
+  for (int w : {2, 4, 8}) {
+    for (int per_cu : {8, 12, 16, 24}) {
+      int nzb = (per_cu * cus + nyo - 1) / nyo;
+      if (nzb > nzo) nzb = nzo;
+      if (nzb < 1) nzb = 1;
+      FastShape sh{w, 1, nzb, 1, 1};
+      bool dup = false;
+      for (int i = 0; i < n; ++i) dup |= out[i].kind == 1 && out[i].W == w && out[i].nzb == nzb;
+      if (!dup && n < max_out && fast_shape_valid(L, p, sh)) out[n++] = sh;
+    }
+  }
   for (int w : kFastW) {
     const int nyb = (nyo + w - 1) / w;
     for (int mult : {1, 2}) {
       int nzb = mult * cus / nyb;
       if (nzb < 1) nzb = 1;
       if (nzb > nzo) nzb = nzo;
-      FastShape sh{w, nyb, nzb};
-      bool dup = false;
-      for (int i = 0; i < n; ++i) dup |= out[i].W == w && out[i].nyb == nyb && out[i].nzb == nzb;
-      if (!dup && n < max_out && fast_shape_valid(L, p, sh)) out[n++] = sh;
+      for (int pf : {1, 2}) {
+        FastShape sh{w, nyb, nzb, pf, 0};
+        bool dup = false;
+        for (int i = 0; i < n; ++i)
+          dup |= out[i].kind == 0 && out[i].W == w && out[i].nyb == nyb && out[i].nzb == nzb && out[i].pf == pf;
+        if (!dup && n < max_out && fast_shape_valid(L, p, sh)) out[n++] = sh;
+      }
     }
   }
   return n;
 }
 
-template <class C, int KX, int W>
+template <class C, int KX, int W, int PF>
 static hipError_t launch_fast_w(const void* src, void* dst, const Fast3DParams& fp, hipStream_t s) {
   using E = typename C::elem;
   const dim3 block(64, W + 2, 1);
-  hipLaunchKernelGGL((step_d3q19_fast<C, KX, W>), dim3(fp.nblocks), block, 0, s, (const E*)src, (E*)dst, fp);
+  hipLaunchKernelGGL((step_d3q19_fast<C, KX, W, PF>), dim3(fp.nblocks), block, 0, s, (const E*)src, (E*)dst, fp);
   return hipGetLastError();
 }
 
-template <class C, int KX>
-static hipError_t launch_fast_kx(int W, const void* src, void* dst, const Fast3DParams& fp, hipStream_t s) {
+template <class C, int KX, int PF>
+static hipError_t launch_fast_pf(int W, const void* src, void* dst, const Fast3DParams& fp, hipStream_t s) {
   switch (W) {
-    case 4: return launch_fast_w<C, KX, 4>(src, dst, fp, s);
-    case 6: return launch_fast_w<C, KX, 6>(src, dst, fp, s);
-    case 8: return launch_fast_w<C, KX, 8>(src, dst, fp, s);
-    case 10: return launch_fast_w<C, KX, 10>(src, dst, fp, s);
-    case 12: return launch_fast_w<C, KX, 12>(src, dst, fp, s);
+    case 4: return launch_fast_w<C, KX, 4, PF>(src, dst, fp, s);
+    case 6: return launch_fast_w<C, KX, 6, PF>(src, dst, fp, s);
+    case 8: return launch_fast_w<C, KX, 8, PF>(src, dst, fp, s);
+    case 10: return launch_fast_w<C, KX, 10, PF>(src, dst, fp, s);
+    case 12:
+      if constexpr (PF == 1) return launch_fast_w<C, KX, 12, PF>(src, dst, fp, s);
+      break;
   }
   return hipErrorInvalidValue;
 }
 
+template <class C, int KX, int NWV>
+static hipError_t launch_indep_w(const void* src, void* dst, const Fast3DParams& fp, hipStream_t s) {
+  using E = typename C::elem;
+  if constexpr (KX == 1) {
+    hipLaunchKernelGGL((step_d3q19_indep<C, KX, NWV>), dim3(fp.nblocks), dim3(64, NWV, 1), 0, s, (const E*)src,
+                       (E*)dst, fp);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class C, int KX>
+static hipError_t launch_fast_kx(const FastShape& sh, const void* src, void* dst, const Fast3DParams& fp,
+                                 hipStream_t s) {
+  if (sh.kind == 1) {
+    switch (sh.W) {
+      case 1: return launch_indep_w<C, KX, 1>(src, dst, fp, s);
+      case 2: return launch_indep_w<C, KX, 2>(src, dst, fp, s);
+      case 4: return launch_indep_w<C, KX, 4>(src, dst, fp, s);
+      case 8: return launch_indep_w<C, KX, 8>(src, dst, fp, s);
+    }
+    return hipErrorInvalidValue;
+  }
+  return sh.pf == 2 ? launch_fast_pf<C, KX, 2>(sh.W, src, dst, fp, s) : launch_fast_pf<C, KX, 1>(sh.W, src, dst, fp, s);
+}
+
 template <class C>
-static hipError_t launch_fast_codec(const Layout& L, int W, const void* src, void* dst, const Fast3DParams& fp,
-                                    hipStream_t s) {
+static hipError_t launch_fast_codec(const Layout& L, const FastShape& sh, const void* src, void* dst,
+                                    const Fast3DParams& fp, hipStream_t s) {
   switch (L.nx) {
-    case 64: return launch_fast_kx<C, 1>(W, src, dst, fp, s);
-    case 128: return launch_fast_kx<C, 2>(W, src, dst, fp, s);
-    case 256: return launch_fast_kx<C, 4>(W, src, dst, fp, s);
+    case 64: return launch_fast_kx<C, 1>(sh, src, dst, fp, s);
+    case 128: return launch_fast_kx<C, 2>(sh, src, dst, fp, s);
+    case 256: return launch_fast_kx<C, 4>(sh, src, dst, fp, s);
   }
   return hipErrorInvalidValue;
 }
@@ -463,18 +703,22 @@ hipError_t launch_step_fast(const Layout& L, const void* src, void* dst, const S
   fp.zlo = fp.zper ? 0 : 1;
   fp.nyb = sh.nyb;
   fp.nzb = sh.nzb;
-  fp.nblocks = sh.nyb * sh.nzb;
+  if (sh.kind == 1) {
+    const int64_t waves = (int64_t)fp.nyo * sh.nzb;
+    fp.nblocks = (int)((waves + sh.W - 1) / sh.W);
+  } else {
+    fp.nblocks = sh.nyb * sh.nzb;
+  }
   fp.plane = L.plane;
   fp.rho_ref = (float)p.rho_ref;
   fp.gx = (float)p.g[0];
   fp.gy = (float)p.g[1];
   fp.gz = (float)p.g[2];
-  fp.seed = p.seed;
-  fp.step = p.step;
+  fp.sr_key = p.sr_key;
   switch (L.precision) {
-    case MACLAB_FP32: return launch_fast_codec<CodecF32>(L, sh.W, src, dst, fp, s);
-    case MACLAB_HILO: return launch_fast_codec<CodecHILO>(L, sh.W, src, dst, fp, s);
-    case MACLAB_S16: return launch_fast_codec<CodecS16>(L, sh.W, src, dst, fp, s);
+    case MACLAB_FP32: return launch_fast_codec<CodecF32>(L, sh, src, dst, fp, s);
+    case MACLAB_HILO: return launch_fast_codec<CodecHILO>(L, sh, src, dst, fp, s);
+    case MACLAB_S16: return launch_fast_codec<CodecS16>(L, sh, src, dst, fp, s);
   }
   return hipErrorInvalidValue;
 }

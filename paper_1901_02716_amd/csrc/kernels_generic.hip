@@ -23,10 +23,8 @@ __device__ __forceinline__ typename C::T load_field(const typename C::elem* base
 
 template <class C>
 __device__ __forceinline__ void store_field(typename C::elem* base, int64_t plane, int f, int64_t node,
-                                            typename C::T v, const StepParams& p) {
-  uint32_t r = 0;
-  if constexpr (needs_rng<C>::value) r = sr_bits(p.seed, p.step, node, f);
-  base[f * plane + node] = C::enc(v, f, r);
+                                            typename C::T v, uint32_t node_bits) {
+  base[f * plane + node] = C::enc(v, f, node_bits);
 }
 
 __device__ __forceinline__ int64_t wrap_idx(int64_t v, int64_t n) {
@@ -75,10 +73,12 @@ __global__ __launch_bounds__(256) void step_generic_kernel(const typename C::ele
   }
   const T inv = (T)1 / (rho_ref + drho);
   const int64_t x = i + p.nx * (j + p.ny * k);
-  store_field<C>(dst, p.plane, 0, x, drho, p);
-  store_field<C>(dst, p.plane, 1, x, (mx + (T)p.g[0]) * inv, p);
-  store_field<C>(dst, p.plane, 2, x, (my + (T)p.g[1]) * inv, p);
-  if constexpr (D == 3) store_field<C>(dst, p.plane, 3, x, (mz + (T)p.g[2]) * inv, p);
+  uint32_t bits = 0;
+  if constexpr (needs_rng<C>::value) bits = sr_node_bits(p.sr_key, x);
+  store_field<C>(dst, p.plane, 0, x, drho, bits);
+  store_field<C>(dst, p.plane, 1, x, (mx + (T)p.g[0]) * inv, bits);
+  store_field<C>(dst, p.plane, 2, x, (my + (T)p.g[1]) * inv, bits);
+  if constexpr (D == 3) store_field<C>(dst, p.plane, 3, x, (mz + (T)p.g[2]) * inv, bits);
 }
 
 // Writes the fixed-face values into both buffers; a node on several fixed
@@ -98,8 +98,8 @@ __global__ void impose_bc_kernel(typename C::elem* b0, typename C::elem* b1, int
   }
   if (face < 0) return;
   typename C::elem v[4];
-  v[0] = C::enc((typename C::T)(fv.rho[face] - rho_ref), 0, 0x1000u);
-  for (int c = 0; c < d; ++c) v[1 + c] = C::enc((typename C::T)(fv.u[face][c] / e), 1 + c, 0x1000u);
+  v[0] = C::enc((typename C::T)(fv.rho[face] - rho_ref), 0, kRoundNearestBits);
+  for (int c = 0; c < d; ++c) v[1 + c] = C::enc((typename C::T)(fv.u[face][c] / e), 1 + c, kRoundNearestBits);
   for (int f = 0; f <= d; ++f) {
     b0[f * plane + x] = v[f];
     b1[f * plane + x] = v[f];
@@ -112,7 +112,7 @@ __global__ void encode_kernel(typename C::elem* dst, const double* __restrict__ 
                               double offset, double mul, int field) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
-  dst[i] = C::enc((typename C::T)((src[i] - offset) * mul), field, 0x1000u);
+  dst[i] = C::enc((typename C::T)((src[i] - offset) * mul), field, kRoundNearestBits);
 }
 
 // Stored -> physical float64: dst = offset + mul * value.

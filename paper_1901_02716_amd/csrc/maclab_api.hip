@@ -129,6 +129,7 @@ StepParams make_params(const maclab_t h) {
   for (int i = 0; i < 3; ++i) p.g[i] = (i < h->L.d) ? h->dt * h->cfg.body_force[i] / h->e : 0.0;
   p.seed = h->cfg.seed;
   p.step = (uint64_t)h->steps;
+  p.sr_key = sr_key(p.seed, p.step);
   return p;
 }
 
@@ -272,6 +273,7 @@ int maclab_step(maclab_t h, int64_t n) {
   }
   for (int64_t s = 0; s < n; ++s) {
     p.step = (uint64_t)h->steps;
+    p.sr_key = sr_key(p.seed, p.step);
     const void* src = h->state[h->cur];
     void* dst = h->state[h->cur ^ 1];
     if (fast)
@@ -377,32 +379,35 @@ int maclab_load_state(maclab_t h, const void* src) {
   return MACLAB_OK;
 }
 
-int maclab_get_tiling(maclab_t h, int out[4]) {
+int maclab_get_tiling(maclab_t h, int out[5]) {
+  // out = {kernel, W, nyb, nzb, pf}; kernel 1 = LDS exchange, 2 = independent
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
   if (!out) return fail(h, MACLAB_EINVAL, "out is NULL");
   StepParams p = make_params(h);
   if (!fast_step_supported(h->L, p)) {
     out[0] = 0;
-    out[1] = out[2] = out[3] = 0;
+    out[1] = out[2] = out[3] = out[4] = 0;
     return MACLAB_OK;
   }
   const FastShape sh = (h->shape_set && fast_shape_valid(h->L, p, h->shape)) ? h->shape
                                                                              : fast_default_shape(h->L, p, h->cus);
-  out[0] = 1;
+  out[0] = 1 + sh.kind;
   out[1] = sh.W;
   out[2] = sh.nyb;
   out[3] = sh.nzb;
+  out[4] = sh.pf;
   return MACLAB_OK;
 }
 
-int maclab_set_tiling(maclab_t h, int W, int nyb, int nzb) {
+int maclab_set_tiling(maclab_t h, int kernel, int W, int nyb, int nzb, int pf) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (kernel != 1 && kernel != 2) return fail(h, MACLAB_EINVAL, "kernel must be 1 or 2");
   StepParams p = make_params(h);
   if (!fast_step_supported(h->L, p))
     return fail(h, MACLAB_EUNSUPPORTED, "this lattice runs the general kernel, which has no tiling");
-  FastShape sh{W, nyb, nzb};
+  FastShape sh{W, nyb, nzb, pf, kernel - 1};
   if (!fast_shape_valid(h->L, p, sh))
-    return fail(h, MACLAB_EINVAL, "invalid tiling W=%d nyb=%d nzb=%d", W, nyb, nzb);
+    return fail(h, MACLAB_EINVAL, "invalid tiling W=%d nyb=%d nzb=%d pf=%d", W, nyb, nzb, pf);
   h->shape = sh;
   h->shape_set = true;
   return MACLAB_OK;
@@ -417,16 +422,17 @@ int maclab_autotune(maclab_t h, int reps, double* best_ms) {
   const void* src = h->state[h->cur];
   void* dst = h->state[h->cur ^ 1];  // scratch output: the state is not advanced
   const bool fast = fast_step_supported(h->L, p);
-  FastShape cand[16];
+  FastShape cand[48];
   int nc = 0;
   if (fast) {
     cand[nc++] = fast_default_shape(h->L, p, h->cus);
-    FastShape more[16];
-    const int nm = fast_candidates(h->L, p, h->cus, more, 16);
-    for (int i = 0; i < nm && nc < 16; ++i) {
+    FastShape more[48];
+    const int nm = fast_candidates(h->L, p, h->cus, more, 48);
+    for (int i = 0; i < nm && nc < 48; ++i) {
       bool dup = false;
       for (int j = 0; j < nc; ++j)
-        dup |= cand[j].W == more[i].W && cand[j].nyb == more[i].nyb && cand[j].nzb == more[i].nzb;
+        dup |= cand[j].W == more[i].W && cand[j].nyb == more[i].nyb && cand[j].nzb == more[i].nzb &&
+               cand[j].pf == more[i].pf && cand[j].kind == more[i].kind;
       if (!dup) cand[nc++] = more[i];
     }
   } else {

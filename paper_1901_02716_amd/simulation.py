@@ -134,12 +134,14 @@ class Simulation:
 
     # -------------------------------------------------------------- tiling
     def tiling(self) -> dict:
-        out = (ctypes.c_int * 4)()
+        out = (ctypes.c_int * 5)()
         _lib.check(self.lib.maclab_get_tiling(self.h, out), self.h)
-        return {"kernel": ("general", "fast3d")[out[0]], "W": out[1], "nyb": out[2], "nzb": out[3]}
+        kinds = ("general", "exchange", "independent")
+        return {"kernel": kinds[out[0]], "W": out[1], "nyb": out[2], "nzb": out[3], "pf": out[4]}
 
-    def set_tiling(self, W: int, nyb: int, nzb: int) -> None:
-        _lib.check(self.lib.maclab_set_tiling(self.h, int(W), int(nyb), int(nzb)), self.h)
+    def set_tiling(self, W: int, nyb: int, nzb: int, pf: int = 1, kernel: str = "exchange") -> None:
+        k = {"exchange": 1, "independent": 2}[kernel]
+        _lib.check(self.lib.maclab_set_tiling(self.h, k, int(W), int(nyb), int(nzb), int(pf)), self.h)
 
     def autotune(self, reps: int = 10) -> float:
         """Picks the fastest tiling (the state does not advance); returns ms/step."""

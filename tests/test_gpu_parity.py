@@ -314,10 +314,15 @@ def _tilings(nyo, nzo):
     for W in (4, 6, 8, 10, 12):
         nyb = -(-nyo // W)
         for nzb in sorted({1, 3, nzo}):
-            out.append((W, nyb, nzb))
-    out.append((4, nyo, 2))      # one row per block, idle wavefronts
-    out.append((12, nyo, nzo))  # one row and one plane per block
-    return out
+            out.append((W, nyb, nzb, 2 if nzb == 3 and W <= 10 else 1))
+    out.append((4, nyo, 2, 1))      # one row per block, idle wavefronts
+    out.append((12, nyo, nzo, 1))  # one row and one plane per block
+    out.append((8, -(-nyo // 8), 1, 2))
+    return [t + ("exchange",) for t in out]
+
+
+def _indep_tilings(nzo):
+    return [(w, 1, nzb, 1, "independent") for w in (1, 4, 8) for nzb in sorted({1, 2, nzo})]
 
 
 @pytest.mark.parametrize("name,nx,nyz,walls,G", [FAST[0], FAST[1], FAST[3]], ids=[FAST[i][0] for i in (0, 1, 3)])
@@ -329,10 +334,11 @@ def test_fast_path_every_tiling_is_bitwise_identical(name, nx, nyz, walls, G):
     nyo = nyz[0] - 2 if "y" in walls else nyz[0]
     nzo = nyz[1] - 2 if "z" in walls else nyz[1]
     ref = None
-    for W, nyb, nzb in _tilings(nyo, nzo):
+    tilings = _tilings(nyo, nzo) + (_indep_tilings(nzo) if nx == 64 else [])
+    for W, nyb, nzb, pf, kern in tilings:
         sim = make_sim(case, "fp32")
-        sim.set_tiling(W, nyb, nzb)
-        assert sim.tiling() == {"kernel": "fast3d", "W": W, "nyb": nyb, "nzb": nzb}
+        sim.set_tiling(W, nyb, nzb, pf, kern)
+        assert sim.tiling() == {"kernel": kern, "W": W, "nyb": nyb, "nzb": nzb, "pf": pf}
         sim.step(6)
         st = sim.save_state()
         if ref is None:
@@ -341,20 +347,28 @@ def test_fast_path_every_tiling_is_bitwise_identical(name, nx, nyz, walls, G):
             orho, ou = oracle.run(to_problem(case), case.rho, case.u, 6)
             assert rel_l2(u, ou) < 1e-5 and rel_l2(rho, orho) < 1e-5
         else:
-            assert torch.equal(st, ref), (W, nyb, nzb)
+            assert torch.equal(st, ref), (W, nyb, nzb, pf, kern)
 
 
 def test_invalid_tiling_rejected():
     case = _fast_case(64, (37, 29), ("x", "y", "z"), (0, 0, 0))
     sim = make_sim(case, "fp32")
-    for bad in ((5, 5, 5), (4, 2, 5), (8, 0, 1), (8, 5, 28)):
+    for bad in ((5, 5, 5, 1), (4, 2, 5, 1), (8, 0, 1, 1), (8, 5, 28, 1), (8, 5, 5, 3), (12, 3, 5, 2)):
         with pytest.raises(MaclabError) as ei:
             sim.set_tiling(*bad)
         assert ei.value.code == _lib.EINVAL
+    for bad in ((3, 1, 5, 1), (4, 2, 5, 1), (4, 1, 28, 1), (4, 1, 5, 2)):
+        with pytest.raises(MaclabError) as ei:
+            sim.set_tiling(*bad, kernel="independent")
+        assert ei.value.code == _lib.EINVAL
+    wide = make_sim(_fast_case(128, (11, 10), ("x", "y", "z"), (0, 0, 0)), "fp32")
+    with pytest.raises(MaclabError) as ei:
+        wide.set_tiling(4, 1, 2, 1, "independent")  # nx = 128: exchange kernel only
+    assert ei.value.code == _lib.EINVAL
     gen = make_sim(workloads.cavity_3d(n=20, Re=10.0), "fp32")
     assert gen.tiling()["kernel"] == "general"
     with pytest.raises(MaclabError) as ei:
-        gen.set_tiling(8, 3, 3)
+        gen.set_tiling(8, 3, 3, 1, "exchange")
     assert ei.value.code == _lib.EUNSUPPORTED
 
 
