@@ -147,21 +147,26 @@ size_t maclab_state_bytes(maclab_t h);
 int maclab_save_state(maclab_t h, void* dst_device);
 int maclab_load_state(maclab_t h, const void* src_device);
 
-/* Kernel tiling. out[5] = {kernel, W, nyb, nzb, pf}. kernel 0 is the
- * general kernel (any shape; no tiling). The fast D3Q19 kernels (x extent
- * 64, 128 or 256; FP32 arithmetic) march each x-row in z with one wavefront
- * per row:
- *  kernel 1 (LDS exchange): workgroups of W output rows (W in {4,6,8,10,12})
- *    plus two halo rows exchange the y-links through LDS; nyb x nzb
- *    workgroups with balanced (y, z) ranges; pf (1 or 2, 2 only for W <= 10)
- *    source planes loaded ahead. Needs ceil(rows / nyb) <= W.
- *  kernel 2 (independent wavefronts, x extent 64 only): each wavefront owns
- *    one row and one of nzb balanced z-chunks and evaluates the links of the
- *    neighbouring rows it needs itself (no LDS, no barriers); W in {1,2,4,8}
- *    wavefronts per workgroup; nyb = pf = 1.
- * set_tiling validates (nyb <= rows, nzb <= planes) and returns
- * MACLAB_EUNSUPPORTED for lattices on the general kernel. Both fast kernels
- * and every valid tiling give bitwise identical results. */
+/* Kernel and tiling of the step. out[5] = {kernel, W, nyb, nzb, pf}.
+ *  kernel 0: general kernel (any shape and boundaries; no tiling).
+ *  kernel 1: fast D3Q19, LDS exchange (x extent 64, 128 or 256; FP32
+ *    arithmetic): one wavefront per x-row marches in z; workgroups of W
+ *    output rows (W in {4,6,8,10,12}) plus two halo rows exchange the
+ *    y-links through LDS; nyb x nzb workgroups with balanced (y, z) ranges;
+ *    pf (1 or 2, 2 only with W <= 10) source planes loaded ahead. Needs
+ *    ceil(rows / nyb) <= W.
+ *  kernel 2: fast D3Q19, independent wavefronts (x extent 64 only): each
+ *    wavefront owns one row and one of nzb balanced z-chunks and evaluates
+ *    the links of the neighbouring rows it needs itself (no LDS, no
+ *    barriers); W in {1,2,4,8} wavefronts per workgroup; nyb = pf = 1.
+ *  kernel 3: fast D2Q9 (walled x of any extent, or periodic x whose extent
+ *    is a multiple of 64*W): one wavefront per (x-segment of 64*W nodes,
+ *    band of rows), W in {1,2}; nzb bands; nyb (reported: segments per
+ *    row) and pf are ignored.
+ * set_tiling validates (nyb <= rows, nzb <= planes or bands <= rows) and
+ * returns MACLAB_EUNSUPPORTED when the kernel does not handle the lattice.
+ * Kernels 1 and 2 and every valid tiling of a kernel give bitwise identical
+ * results. */
 int maclab_get_tiling(maclab_t h, int out[5]);
 int maclab_set_tiling(maclab_t h, int kernel, int W, int nyb, int nzb, int pf);
 

@@ -22,21 +22,35 @@ def sources() -> list[str]:
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def command(out: str = LIB) -> list[str]:
-    return ["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-Wall", "-I", os.path.join(ROOT, "include"), *sources(), "-o", out]
+FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall"]
 
 
-def build_library(out: str = LIB, verbose: bool = False) -> str:
-    """Compiles every kernel and the C ABI into one shared library."""
-    tmp = out + ".tmp"
-    cmd = command(tmp)
+def _run(cmd: list[str]) -> str:
     res = subprocess.run(cmd, capture_output=True, text=True)
     noise = "packed-fp32-ops"
     msg = "\n".join(ln for ln in (res.stdout + res.stderr).splitlines() if noise not in ln)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + msg)
+    return msg
+
+
+def build_library(out: str = LIB, verbose: bool = False) -> str:
+    """Compiles every kernel and the C ABI (one hipcc per source, in
+    parallel) and links them into one shared library."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+
+    inc = ["-I", os.path.join(ROOT, "include")]
+    with tempfile.TemporaryDirectory(prefix="maclab_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.basename(src) + ".o") for src in sources()]
+        jobs = [["hipcc", *FLAGS, *inc, "-c", src, "-o", obj] for src, obj in zip(sources(), objs)]
+        workers = min(len(jobs), max(1, min(8, os.cpu_count() or 1)))
+        with ThreadPoolExecutor(workers) as ex:
+            msgs = list(ex.map(_run, jobs))
+        tmp = out + ".tmp"
+        msgs.append(_run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]))
+    msg = "\n".join(m for m in msgs if m.strip())
     if verbose and msg.strip():
         print(msg, file=sys.stderr)
     os.replace(tmp, out)

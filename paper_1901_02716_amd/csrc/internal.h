@@ -65,4 +65,16 @@ int fast_candidates(const Layout& L, const StepParams& p, int cus, FastShape* ou
 hipError_t launch_step_fast(const Layout& L, const void* src, void* dst, const StepParams& p, const FastShape& sh,
                             hipStream_t s);
 
+// Fast D2Q9 path (kernels_2d.hip): one wavefront per (x-segment of 64*kx
+// nodes, band of rows); nband bands per segment.
+struct Fast2DShape {
+  int kx = 4, nband = 1;
+};
+bool fast2d_supported(const Layout& L, const StepParams& p);
+bool fast2d_shape_valid(const Layout& L, const StepParams& p, const Fast2DShape& sh);
+Fast2DShape fast2d_default_shape(const Layout& L, const StepParams& p, int cus);
+int fast2d_candidates(const Layout& L, const StepParams& p, int cus, Fast2DShape* out, int max_out);
+hipError_t launch_step_fast2d(const Layout& L, const void* src, void* dst, const StepParams& p,
+                              const Fast2DShape& sh, hipStream_t s);
+
 }  // namespace maclab

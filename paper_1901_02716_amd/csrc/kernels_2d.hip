@@ -1,0 +1,404 @@
+// Fast D2Q9 MacLAB step for gfx950, for one lattice or a batch of lattices.
+//
+// Work decomposition
+//  - A work item is (lattice, x-segment, band of rows). One wavefront takes
+//    one item: lane l holds the KX consecutive nodes x0 + KX*l .. + KX-1 of
+//    the segment (64*KX nodes wide) and the wavefront marches up the rows of
+//    its band, keeping three rolling row accumulators (rows y-1, y, y+1).
+//  - Each node computes the equilibria of its 9 links once (Eq. (2) in the
+//    deviation form F^_a = f_eq_a - w_a rho_ref, times 36) and pushes them to
+//    x + c_a: the y shift is the rolling accumulator, the x shift an in-lane
+//    move or a DPP wave rotate across lanes. At the edges of a segment that
+//    does not span the whole row, the two lanes at the edges also evaluate
+//    the links of the neighbouring node outside the segment.
+//  - After source row y is pushed, destination row y-1 holds the gathers of
+//    Eqs. (4)-(5): rho' = rho_ref + drho', u~' = (m' + g) / rho'.
+//  - There is no LDS and no barrier; every wavefront works alone.
+//  - Contraction is off and every FMA is written out, so results do not
+//    depend on the segmentation or banding.
+#include "internal.h"
+
+namespace maclab {
+
+// Where a lattice lives in memory and how its boundaries behave.
+struct Lattice2D {
+  int nx, ny, pitch;  // node counts; elements between rows (>= nx)
+  int xper, yper;     // periodic axes (else both faces fixed)
+  int aligned;        // rows start on a KX-element boundary (vector loads)
+  double gx, gy;      // dt G / e
+  int64_t base;       // element offset of the lattice's first field plane
+  int64_t plane;      // elements between field planes
+};
+
+struct Fast2DParams {
+  const Lattice2D* lat;  // device array (batch) ...
+  Lattice2D one;         // ... or this single lattice when lat == nullptr
+  const int4* items;     // device array of work items {lattice, x0, y0, y1} ...
+  int nseg, nband;       // ... or, when items == nullptr, segments x bands of `one`
+  int nyo, ylo;          //     (output rows nyo from ylo, split into nband bands)
+  int nitems;
+  double rho_ref;
+  uint32_t sr_key;
+};
+
+template <class T>
+struct Links2 {
+  T f0, qxp, qxm, qyp, qym;  // rest, and the axis links divided by 4
+  T pp, mm, pm, mp;          // (1,1) (-1,-1) (1,-1) (-1,1)
+};
+
+// The 9 link values of one node, times 36: 36 F^_a = wnum_a [a + c.b +
+// sum_i c_i^2 q_ii + c_x c_y q_xy] with a = drho - 1.5 rho |u|^2, b = 3 rho u,
+// q_ii = 4.5 rho u_i^2, q_xy = 9 rho u_x u_y (wnum = 16, 4, 1).
+template <class T>
+__device__ __forceinline__ void links2(T dr, T ux, T uy, T rho_ref, Links2<T>& L) {
+#pragma clang fp contract(off)
+  const T rho = rho_ref + dr;
+  const T r3 = (T)3 * rho;
+  const T bx = r3 * ux, by = r3 * uy;
+  const T cxx = bx * ux, cyy = by * uy, cxy = bx * uy;  // 3 rho u_i u_j
+  const T a = __builtin_fma(cxx + cyy, (T)-0.5, dr);
+  const T sx = __builtin_fma(cxx, (T)1.5, a), sy = __builtin_fma(cyy, (T)1.5, a);
+  L.f0 = (T)16 * a;
+  L.qxp = sx + bx;
+  L.qxm = sx - bx;
+  L.qyp = sy + by;
+  L.qym = sy - by;
+  const T t = __builtin_fma(cyy, (T)1.5, sx);
+  const T p = __builtin_fma(cxy, (T)3, t), m = __builtin_fma(cxy, (T)-3, t);
+  const T u = bx + by, v = bx - by;
+  L.pp = p + u;
+  L.mm = p - u;
+  L.pm = m + v;
+  L.mp = m - v;
+}
+
+template <class E, int KX>
+struct alignas(sizeof(E) * KX) RowVec2 {
+  E v[KX];
+};
+
+template <class T, int KX>
+struct RowAcc2 {
+  T r[KX], mx[KX], my[KX];  // 36 * (drho', m')
+};
+
+__device__ __forceinline__ float dpp_from_left(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x13C, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float dpp_from_right(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double dpp_from_left(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) & 0xffffffff), 0x13C, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) >> 32), 0x13C, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double dpp_from_right(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) & 0xffffffff), 0x134, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) >> 32), 0x134, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wavefronts per SIMD the register budget must allow (keeps the scheduler
+// from spending registers on hoisting).
+template <class C, int KX>
+struct Occupancy2D {
+  static constexpr int value = (sizeof(typename C::T) == 8 && KX > 1) ? 2 : 4;
+};
+
+template <class C, int KX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy2D<C, KX>::value)))
+void step_d2q9_fast(const typename C::elem* __restrict__ src,
+                                                      typename C::elem* __restrict__ dst, Fast2DParams p) {
+  using T = typename C::T;
+  using E = typename C::elem;
+  constexpr int SW = 64 * KX;
+  const int lane = threadIdx.x & 63;
+  // the work item is uniform across the wavefront: keep it in scalar registers
+  const int g = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  if (g >= p.nitems) return;
+  Lattice2D lt;
+  int x0, y0, y1;
+  if (p.items) {
+    const int4 it = p.items[g];
+    lt = p.lat[it.x];
+    x0 = it.y;
+    y0 = it.z;
+    y1 = it.w;
+  } else {
+    lt = p.one;
+    const int seg = g % p.nseg, band = g / p.nseg;
+    x0 = seg * SW;
+    y0 = p.ylo + (int)((int64_t)band * p.nyo / p.nband);
+    y1 = p.ylo + (int)((int64_t)(band + 1) * p.nyo / p.nband);
+  }
+  const E* s = src + lt.base;
+  E* d = dst + lt.base;
+  const T rho_ref = (T)p.rho_ref;
+  const int xb = x0 + KX * lane;
+  // the segment spans the row (one wavefront): neighbours wrap through DPP;
+  // otherwise the edge lanes evaluate the node just outside the segment
+  // (wrapping on a periodic axis, whose extent is then a multiple of 64*KX)
+  const bool full_row = x0 == 0 && lt.nx == SW;
+  const bool need_left = !full_row && (x0 > 0 || lt.xper);
+  const bool need_right = !full_row && (x0 + SW < lt.nx || lt.xper);
+  auto ywrap = [&](int y) { return lt.yper ? (y + lt.ny) % lt.ny : y; };
+
+  T dr[KX], ux[KX], uy[KX];
+  T hdr = 0, hux = 0, huy = 0;  // halo node of lanes 0 / 63
+  const bool vec = lt.aligned && xb + KX <= lt.nx;
+  auto load_row = [&](int y) {
+    const int64_t rb = (int64_t)lt.pitch * ywrap(y);
+    if (vec) {
+      const RowVec2<E, KX> a = *reinterpret_cast<const RowVec2<E, KX>*>(s + rb + xb);
+      const RowVec2<E, KX> b = *reinterpret_cast<const RowVec2<E, KX>*>(s + lt.plane + rb + xb);
+      const RowVec2<E, KX> c = *reinterpret_cast<const RowVec2<E, KX>*>(s + 2 * lt.plane + rb + xb);
+#pragma unroll
+      for (int e = 0; e < KX; ++e) {
+        dr[e] = C::dec(a.v[e], 0);
+        ux[e] = C::dec(b.v[e], 1);
+        uy[e] = C::dec(c.v[e], 2);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < KX; ++e) {
+        int x = xb + e;
+        x = x < lt.nx ? x : lt.nx - 1;  // lanes past a ragged end read a valid node
+        dr[e] = C::dec(s[rb + x], 0);
+        ux[e] = C::dec(s[lt.plane + rb + x], 1);
+        uy[e] = C::dec(s[2 * lt.plane + rb + x], 2);
+      }
+    }
+    if ((lane == 0 && need_left) || (lane == 63 && need_right)) {
+      int hx = lane == 0 ? x0 - 1 : x0 + SW;
+      hx = hx < 0 ? hx + lt.nx : (hx >= lt.nx ? hx - lt.nx : hx);
+      hdr = C::dec(s[rb + hx], 0);
+      hux = C::dec(s[lt.plane + rb + hx], 1);
+      huy = C::dec(s[2 * lt.plane + rb + hx], 2);
+    }
+  };
+
+  RowAcc2<T, KX> A0, A1, A2;
+#pragma unroll
+  for (int e = 0; e < KX; ++e) A0.r[e] = A0.mx[e] = A0.my[e] = A1.r[e] = A1.mx[e] = A1.my[e] = (T)0;
+
+  // Source row ys into rows ys-1 (am), ys (ac), ys+1 (ap, first touched here).
+  // Destination node d needs its own links (rest, +-y), the +x-moving links
+  // of node d-1 (P) and the -x-moving links of node d+1 (M); it is completed
+  // as soon as node d+1 has been evaluated, so few link values stay live.
+  auto source_row = [&](int ys, RowAcc2<T, KX>& am, RowAcc2<T, KX>& ac, RowAcc2<T, KX>& ap) {
+#pragma clang fp contract(off)
+    T of0[KX], oyp[KX], oym[KX];   // own links of node e
+    T pq[KX], ppp[KX], ppm[KX];    // P links of node e: (1,0)/4, (1,1), (1,-1)
+    T mq[KX], mmp[KX], mmm[KX];    // M links of node e: (-1,0)/4, (-1,1), (-1,-1)
+    auto complete = [&](int q, T Pq, T Ppp, T Ppm, T Mq, T Mmp, T Mmm) {
+      // row ys: rest, +-x
+      ac.r[q] += __builtin_fma((T)4, Pq + Mq, of0[q]);
+      ac.mx[q] = __builtin_fma((T)4, Pq - Mq, ac.mx[q]);
+      // row ys+1: +y, +x+y, -x+y
+      const T sp = __builtin_fma((T)4, oyp[q], Ppp + Mmp);
+      ap.r[q] = sp;
+      ap.my[q] = sp;
+      ap.mx[q] = Ppp - Mmp;
+      // row ys-1: -y, +x-y, -x-y
+      const T sm = __builtin_fma((T)4, oym[q], Ppm + Mmm);
+      am.r[q] += sm;
+      am.my[q] -= sm;
+      am.mx[q] += Ppm - Mmm;
+    };
+#pragma unroll
+    for (int e = 0; e < KX; ++e) {
+      Links2<T> L;
+      links2<T>(dr[e], ux[e], uy[e], rho_ref, L);
+      of0[e] = L.f0;
+      oyp[e] = L.qyp;
+      oym[e] = L.qym;
+      pq[e] = L.qxp;
+      ppp[e] = L.pp;
+      ppm[e] = L.pm;
+      mq[e] = L.qxm;
+      mmp[e] = L.mp;
+      mmm[e] = L.mm;
+      if (e >= 2) complete(e - 1, pq[e - 2], ppp[e - 2], ppm[e - 2], mq[e], mmp[e], mmm[e]);
+    }
+    Links2<T> H;
+    links2<T>(hdr, hux, huy, rho_ref, H);  // meaningful on the edge lanes only
+    if (ys < y1) load_row(ys + 1);
+    // links entering the lane's first node from the left and last node from the right
+    T in_q = dpp_from_left(pq[KX - 1]), in_pp = dpp_from_left(ppp[KX - 1]), in_pm = dpp_from_left(ppm[KX - 1]);
+    T in_mq = dpp_from_right(mq[0]), in_mp = dpp_from_right(mmp[0]), in_mm = dpp_from_right(mmm[0]);
+    if (lane == 0 && need_left) {
+      in_q = H.qxp;
+      in_pp = H.pp;
+      in_pm = H.pm;
+    }
+    if (lane == 63 && need_right) {
+      in_mq = H.qxm;
+      in_mp = H.mp;
+      in_mm = H.mm;
+    }
+    if constexpr (KX == 1) {
+      complete(0, in_q, in_pp, in_pm, in_mq, in_mp, in_mm);
+    } else {
+      complete(0, in_q, in_pp, in_pm, mq[1], mmp[1], mmm[1]);
+      complete(KX - 1, pq[KX - 2], ppp[KX - 2], ppm[KX - 2], in_mq, in_mp, in_mm);
+    }
+    const int yd = ys - 1;
+    if (yd >= y0) {
+      const int64_t rb = (int64_t)lt.pitch * ywrap(yd);
+      RowVec2<E, KX> o0, o1, o2;
+#pragma unroll
+      for (int q = 0; q < KX; ++q) {
+        const T drn = am.r[q] * (T)(1.0 / 36.0);
+        T inv;
+        if constexpr (sizeof(T) == 4)
+          inv = __builtin_amdgcn_rcpf(rho_ref + drn);  // v_rcp_f32, 1 ulp
+        else
+          inv = (T)1 / (rho_ref + drn);
+        const T vx = __builtin_fma(am.mx[q], (T)(1.0 / 36.0), (T)lt.gx) * inv;
+        const T vy = __builtin_fma(am.my[q], (T)(1.0 / 36.0), (T)lt.gy) * inv;
+        uint32_t bits = 0;
+        if constexpr (needs_rng<C>::value) bits = sr_node_bits(p.sr_key, lt.base + rb + xb + q);
+        o0.v[q] = C::enc(drn, 0, bits);
+        o1.v[q] = C::enc(vx, 1, bits);
+        o2.v[q] = C::enc(vy, 2, bits);
+      }
+      const bool edge = !lt.xper && (xb == 0 || xb + KX >= lt.nx);  // holds an x wall or the ragged end
+      if (vec && !edge) {
+        *reinterpret_cast<RowVec2<E, KX>*>(d + rb + xb) = o0;
+        *reinterpret_cast<RowVec2<E, KX>*>(d + lt.plane + rb + xb) = o1;
+        *reinterpret_cast<RowVec2<E, KX>*>(d + 2 * lt.plane + rb + xb) = o2;
+      } else {
+#pragma unroll
+        for (int q = 0; q < KX; ++q) {
+          const int x = xb + q;
+          const bool wall = !lt.xper && (x == 0 || x == lt.nx - 1);
+          if (x < lt.nx && !wall) {
+            d[rb + x] = o0.v[q];
+            d[lt.plane + rb + x] = o1.v[q];
+            d[2 * lt.plane + rb + x] = o2.v[q];
+          }
+        }
+      }
+    }
+  };
+
+  load_row(y0 - 1);
+  for (int ys = y0 - 1; ys <= y1; ys += 3) {
+    source_row(ys, A0, A1, A2);
+    if (ys + 1 > y1) break;
+    source_row(ys + 1, A1, A2, A0);
+    if (ys + 2 > y1) break;
+    source_row(ys + 2, A2, A0, A1);
+  }
+}
+
+// ------------------------------------------------------------------ launch
+bool fast2d_supported(const Layout& L, const StepParams& p) {
+  if (L.q != 9 || L.ny < 3) return false;
+  // periodic x: whole segments only (the extent a multiple of 64)
+  if (!p.fixed[0]) return L.nx % 64 == 0;
+  return L.nx >= 3;
+}
+
+// Wider segments need more registers than a wavefront can hold without
+// spilling (three rolling rows of accumulators per node).
+static bool kx_ok(int kx) { return kx == 1 || kx == 2; }
+
+bool fast2d_shape_valid(const Layout& L, const StepParams& p, const Fast2DShape& sh) {
+  if (!kx_ok(sh.kx) || sh.nband < 1) return false;
+  const int nyo = p.fixed[1] ? (int)L.ny - 2 : (int)L.ny;
+  if (sh.nband > nyo) return false;
+  if (!p.fixed[0] && L.nx % (64 * sh.kx) != 0) return false;
+  return true;
+}
+
+Fast2DShape fast2d_default_shape(const Layout& L, const StepParams& p, int cus) {
+  Fast2DShape sh;
+  sh.kx = L.nx >= 128 ? 2 : 1;
+  while (!p.fixed[0] && L.nx % (64 * sh.kx) != 0) sh.kx /= 2;
+  const int nseg = (int)((L.nx + 64 * sh.kx - 1) / (64 * sh.kx));
+  const int nyo = p.fixed[1] ? (int)L.ny - 2 : (int)L.ny;
+  int nband = (8 * cus + nseg - 1) / nseg;  // about 8 wavefronts per CU
+  if (nband > nyo / 4) nband = nyo / 4;      // at least four rows per band
+  if (nband < 1) nband = 1;
+  sh.nband = nband;
+  return sh;
+}
+
+int fast2d_candidates(const Layout& L, const StepParams& p, int cus, Fast2DShape* out, int max_out) {
+  int n = 0;
+  const int nyo = p.fixed[1] ? (int)L.ny - 2 : (int)L.ny;
+  for (int kx : {1, 2}) {
+    for (int per_cu : {4, 8, 16, 32}) {
+      Fast2DShape sh;
+      sh.kx = kx;
+      const int nseg = (int)((L.nx + 64 * kx - 1) / (64 * kx));
+      int nband = (per_cu * cus + nseg - 1) / nseg;
+      if (nband > nyo) nband = nyo;
+      sh.nband = nband;
+      bool dup = false;
+      for (int i = 0; i < n; ++i) dup |= out[i].kx == kx && out[i].nband == nband;
+      if (!dup && n < max_out && fast2d_shape_valid(L, p, sh)) out[n++] = sh;
+    }
+  }
+  return n;
+}
+
+template <class C, int KX>
+static hipError_t launch2d_kx(const void* src, void* dst, const Fast2DParams& fp, hipStream_t s) {
+  using E = typename C::elem;
+  const unsigned blocks = (unsigned)((fp.nitems + 3) / 4);
+  hipLaunchKernelGGL((step_d2q9_fast<C, KX>), dim3(blocks), dim3(256), 0, s, (const E*)src, (E*)dst, fp);
+  return hipGetLastError();
+}
+
+template <class C>
+static hipError_t launch2d_codec(int kx, const void* src, void* dst, const Fast2DParams& fp, hipStream_t s) {
+  switch (kx) {
+    case 1: return launch2d_kx<C, 1>(src, dst, fp, s);
+    case 2: return launch2d_kx<C, 2>(src, dst, fp, s);
+
+  }
+  return hipErrorInvalidValue;
+}
+
+static hipError_t launch2d(int precision, int kx, const void* src, void* dst, const Fast2DParams& fp, hipStream_t s) {
+  switch (precision) {
+    case MACLAB_FP64: return launch2d_codec<CodecF64>(kx, src, dst, fp, s);
+    case MACLAB_FP32: return launch2d_codec<CodecF32>(kx, src, dst, fp, s);
+    case MACLAB_HILO: return launch2d_codec<CodecHILO>(kx, src, dst, fp, s);
+    case MACLAB_S16: return launch2d_codec<CodecS16>(kx, src, dst, fp, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_step_fast2d(const Layout& L, const void* src, void* dst, const StepParams& p,
+                              const Fast2DShape& sh, hipStream_t s) {
+  if (!fast2d_shape_valid(L, p, sh)) return hipErrorInvalidValue;
+  Fast2DParams fp{};
+  fp.lat = nullptr;
+  fp.items = nullptr;
+  Lattice2D& lt = fp.one;
+  lt.nx = (int)L.nx;
+  lt.ny = (int)L.ny;
+  lt.pitch = (int)L.nx;
+  lt.xper = !p.fixed[0];
+  lt.yper = !p.fixed[1];
+  lt.gx = p.g[0];
+  lt.gy = p.g[1];
+  lt.base = 0;
+  lt.plane = L.plane;
+  lt.aligned = (L.nx % sh.kx) == 0;
+  fp.nseg = (int)((L.nx + 64 * sh.kx - 1) / (64 * sh.kx));
+  fp.nyo = p.fixed[1] ? lt.ny - 2 : lt.ny;
+  fp.ylo = p.fixed[1] ? 1 : 0;
+  fp.nband = sh.nband;
+  fp.nitems = fp.nseg * fp.nband;
+  fp.rho_ref = p.rho_ref;
+  fp.sr_key = p.sr_key;
+  return launch2d(L.precision, sh.kx, src, dst, fp, s);
+}
+
+}  // namespace maclab

@@ -13,6 +13,17 @@
 
 using namespace maclab;
 
+namespace {
+// Which kernel advances the lattice and how it is tiled. kernel 0: general;
+// 1: fast D3Q19, LDS exchange; 2: fast D3Q19, independent wavefronts;
+// 3: fast D2Q9.
+struct Plan {
+  int kernel = 0;
+  FastShape s3;
+  Fast2DShape s2;
+};
+}  // namespace
+
 struct maclab_s {
   maclab_config cfg;
   Layout L;
@@ -26,8 +37,8 @@ struct maclab_s {
   double e = 0, dt = 0;
   int64_t steps = 0;
   int cus = 256;               // compute units of the device
-  FastShape shape;             // tiling of the fast kernel
-  bool shape_set = false;      // chosen by maclab_set_tiling / maclab_autotune
+  Plan plan;                   // kernel and tiling of the step
+  bool plan_set = false;       // chosen by maclab_set_tiling / maclab_autotune
   std::string err;
 };
 
@@ -153,6 +164,71 @@ char* plane_ptr(maclab_t h, int buf, int field) {
   return h->state[buf] + (size_t)field * (size_t)h->L.plane * (size_t)h->L.bytes;
 }
 
+bool plan_valid(const Layout& L, const StepParams& p, const Plan& pl) {
+  switch (pl.kernel) {
+    case 0: return true;
+    case 1:
+    case 2: return fast_step_supported(L, p) && pl.s3.kind == pl.kernel - 1 && fast_shape_valid(L, p, pl.s3);
+    case 3: return fast2d_supported(L, p) && fast2d_shape_valid(L, p, pl.s2);
+  }
+  return false;
+}
+
+Plan plan_default(const Layout& L, const StepParams& p, int cus) {
+  Plan pl;
+  if (fast_step_supported(L, p)) {
+    pl.s3 = fast_default_shape(L, p, cus);
+    pl.kernel = 1 + pl.s3.kind;
+  } else if (fast2d_supported(L, p)) {
+    pl.s2 = fast2d_default_shape(L, p, cus);
+    if (fast2d_shape_valid(L, p, pl.s2)) pl.kernel = 3;
+  }
+  return pl;
+}
+
+int plan_candidates(const Layout& L, const StepParams& p, int cus, Plan* out, int max_out) {
+  int n = 0;
+  out[n++] = plan_default(L, p, cus);
+  if (fast_step_supported(L, p)) {
+    FastShape c[48];
+    const int m = fast_candidates(L, p, cus, c, 48);
+    for (int i = 0; i < m && n < max_out; ++i) {
+      Plan pl;
+      pl.kernel = 1 + c[i].kind;
+      pl.s3 = c[i];
+      out[n++] = pl;
+    }
+  } else if (fast2d_supported(L, p)) {
+    Fast2DShape c[48];
+    const int m = fast2d_candidates(L, p, cus, c, 48);
+    for (int i = 0; i < m && n < max_out; ++i) {
+      Plan pl;
+      pl.kernel = 3;
+      pl.s2 = c[i];
+      out[n++] = pl;
+    }
+  }
+  return n;
+}
+
+hipError_t launch_plan(const Layout& L, const StepParams& p, const Plan& pl, const void* src, void* dst,
+                       hipStream_t s) {
+  switch (pl.kernel) {
+    case 1:
+    case 2: return launch_step_fast(L, src, dst, p, pl.s3, s);
+    case 3: return launch_step_fast2d(L, src, dst, p, pl.s2, s);
+  }
+  return launch_step_generic(L, src, dst, p, s);
+}
+
+const Plan& current_plan(maclab_t h, const StepParams& p) {
+  if (!(h->plan_set && plan_valid(h->L, p, h->plan))) {
+    h->plan = plan_default(h->L, p, h->cus);
+    h->plan_set = false;
+  }
+  return h->plan;
+}
+
 }  // namespace
 
 extern "C" {
@@ -266,20 +342,13 @@ int maclab_step(maclab_t h, int64_t n) {
   int rc = check_faces(h);
   if (rc) return rc;
   StepParams p = make_params(h);
-  const bool fast = fast_step_supported(h->L, p);
-  if (fast && !(h->shape_set && fast_shape_valid(h->L, p, h->shape))) {
-    h->shape = fast_default_shape(h->L, p, h->cus);
-    h->shape_set = false;
-  }
+  const Plan pl = current_plan(h, p);
   for (int64_t s = 0; s < n; ++s) {
     p.step = (uint64_t)h->steps;
     p.sr_key = sr_key(p.seed, p.step);
     const void* src = h->state[h->cur];
     void* dst = h->state[h->cur ^ 1];
-    if (fast)
-      HIP_TRY(h, launch_step_fast(h->L, src, dst, p, h->shape, h->stream));
-    else
-      HIP_TRY(h, launch_step_generic(h->L, src, dst, p, h->stream));
+    HIP_TRY(h, launch_plan(h->L, p, pl, src, dst, h->stream));
     h->cur ^= 1;
     ++h->steps;
   }
@@ -380,36 +449,46 @@ int maclab_load_state(maclab_t h, const void* src) {
 }
 
 int maclab_get_tiling(maclab_t h, int out[5]) {
-  // out = {kernel, W, nyb, nzb, pf}; kernel 1 = LDS exchange, 2 = independent
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
   if (!out) return fail(h, MACLAB_EINVAL, "out is NULL");
   StepParams p = make_params(h);
-  if (!fast_step_supported(h->L, p)) {
-    out[0] = 0;
-    out[1] = out[2] = out[3] = out[4] = 0;
-    return MACLAB_OK;
+  const Plan& pl = current_plan(h, p);
+  out[0] = pl.kernel;
+  out[1] = out[2] = out[3] = out[4] = 0;
+  if (pl.kernel == 1 || pl.kernel == 2) {
+    out[1] = pl.s3.W;
+    out[2] = pl.s3.nyb;
+    out[3] = pl.s3.nzb;
+    out[4] = pl.s3.pf;
+  } else if (pl.kernel == 3) {
+    out[1] = pl.s2.kx;
+    out[2] = (int)((h->L.nx + 64 * pl.s2.kx - 1) / (64 * pl.s2.kx));
+    out[3] = pl.s2.nband;
   }
-  const FastShape sh = (h->shape_set && fast_shape_valid(h->L, p, h->shape)) ? h->shape
-                                                                             : fast_default_shape(h->L, p, h->cus);
-  out[0] = 1 + sh.kind;
-  out[1] = sh.W;
-  out[2] = sh.nyb;
-  out[3] = sh.nzb;
-  out[4] = sh.pf;
   return MACLAB_OK;
 }
 
 int maclab_set_tiling(maclab_t h, int kernel, int W, int nyb, int nzb, int pf) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
-  if (kernel != 1 && kernel != 2) return fail(h, MACLAB_EINVAL, "kernel must be 1 or 2");
   StepParams p = make_params(h);
-  if (!fast_step_supported(h->L, p))
-    return fail(h, MACLAB_EUNSUPPORTED, "this lattice runs the general kernel, which has no tiling");
-  FastShape sh{W, nyb, nzb, pf, kernel - 1};
-  if (!fast_shape_valid(h->L, p, sh))
-    return fail(h, MACLAB_EINVAL, "invalid tiling W=%d nyb=%d nzb=%d pf=%d", W, nyb, nzb, pf);
-  h->shape = sh;
-  h->shape_set = true;
+  Plan pl;
+  pl.kernel = kernel;
+  if (kernel == 1 || kernel == 2) {
+    if (!fast_step_supported(h->L, p))
+      return fail(h, MACLAB_EUNSUPPORTED, "the fast D3Q19 kernels do not handle this lattice");
+    pl.s3 = FastShape{W, nyb, nzb, pf, kernel - 1};
+  } else if (kernel == 3) {
+    if (!fast2d_supported(h->L, p))
+      return fail(h, MACLAB_EUNSUPPORTED, "the fast D2Q9 kernel does not handle this lattice");
+    pl.s2.kx = W;
+    pl.s2.nband = nzb;
+  } else if (kernel != 0) {
+    return fail(h, MACLAB_EINVAL, "kernel must be 0 (general), 1, 2 (D3Q19) or 3 (D2Q9)");
+  }
+  if (!plan_valid(h->L, p, pl))
+    return fail(h, MACLAB_EINVAL, "invalid tiling kernel=%d W=%d nyb=%d nzb=%d pf=%d", kernel, W, nyb, nzb, pf);
+  h->plan = pl;
+  h->plan_set = true;
   return MACLAB_OK;
 }
 
@@ -421,23 +500,8 @@ int maclab_autotune(maclab_t h, int reps, double* best_ms) {
   StepParams p = make_params(h);
   const void* src = h->state[h->cur];
   void* dst = h->state[h->cur ^ 1];  // scratch output: the state is not advanced
-  const bool fast = fast_step_supported(h->L, p);
-  FastShape cand[48];
-  int nc = 0;
-  if (fast) {
-    cand[nc++] = fast_default_shape(h->L, p, h->cus);
-    FastShape more[48];
-    const int nm = fast_candidates(h->L, p, h->cus, more, 48);
-    for (int i = 0; i < nm && nc < 48; ++i) {
-      bool dup = false;
-      for (int j = 0; j < nc; ++j)
-        dup |= cand[j].W == more[i].W && cand[j].nyb == more[i].nyb && cand[j].nzb == more[i].nzb &&
-               cand[j].pf == more[i].pf && cand[j].kind == more[i].kind;
-      if (!dup) cand[nc++] = more[i];
-    }
-  } else {
-    nc = 1;
-  }
+  Plan cand[64];
+  const int nc = plan_candidates(h->L, p, h->cus, cand, 64);
   hipEvent_t e0, e1;
   HIP_TRY(h, hipEventCreate(&e0));
   hipError_t ee = hipEventCreate(&e1);
@@ -449,13 +513,9 @@ int maclab_autotune(maclab_t h, int reps, double* best_ms) {
   int best_i = 0;
   hipError_t err = hipSuccess;
   for (int i = 0; i < nc && err == hipSuccess; ++i) {
-    auto launch = [&]() {
-      return fast ? launch_step_fast(h->L, src, dst, p, cand[i], h->stream)
-                  : launch_step_generic(h->L, src, dst, p, h->stream);
-    };
-    if ((err = launch()) != hipSuccess) break;  // warm-up
+    if ((err = launch_plan(h->L, p, cand[i], src, dst, h->stream)) != hipSuccess) break;  // warm-up
     if ((err = hipEventRecord(e0, h->stream)) != hipSuccess) break;
-    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch();
+    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_plan(h->L, p, cand[i], src, dst, h->stream);
     if (err != hipSuccess) break;
     if ((err = hipEventRecord(e1, h->stream)) != hipSuccess) break;
     if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
@@ -470,10 +530,8 @@ int maclab_autotune(maclab_t h, int reps, double* best_ms) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (err != hipSuccess) return fail(h, MACLAB_EHIP, "maclab_autotune: %s", hipGetErrorString(err));
-  if (fast) {
-    h->shape = cand[best_i];
-    h->shape_set = true;
-  }
+  h->plan = cand[best_i];
+  h->plan_set = true;
   if (best_ms) *best_ms = best;
   return MACLAB_OK;
 }

@@ -136,11 +136,13 @@ class Simulation:
     def tiling(self) -> dict:
         out = (ctypes.c_int * 5)()
         _lib.check(self.lib.maclab_get_tiling(self.h, out), self.h)
-        kinds = ("general", "exchange", "independent")
+        kinds = ("general", "exchange", "independent", "fast2d")
         return {"kernel": kinds[out[0]], "W": out[1], "nyb": out[2], "nzb": out[3], "pf": out[4]}
 
-    def set_tiling(self, W: int, nyb: int, nzb: int, pf: int = 1, kernel: str = "exchange") -> None:
-        k = {"exchange": 1, "independent": 2}[kernel]
+    def set_tiling(self, W: int = 0, nyb: int = 0, nzb: int = 0, pf: int = 1, kernel: str = "exchange") -> None:
+        """kernel: "general", "exchange" / "independent" (D3Q19) or "fast2d"
+        (D2Q9: W = x-segment width / 64, nzb = bands of rows)."""
+        k = {"general": 0, "exchange": 1, "independent": 2, "fast2d": 3}[kernel]
         _lib.check(self.lib.maclab_set_tiling(self.h, k, int(W), int(nyb), int(nzb), int(pf)), self.h)
 
     def autotune(self, reps: int = 10) -> float:

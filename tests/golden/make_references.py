@@ -1,0 +1,105 @@
+"""Writes the long-run oracle references used by the GPU parity tests.
+
+Every value stored here comes from the FP64 CPU oracle (``oracle/``) on inputs
+from ``paper_1901_02716_amd.workloads``; nothing is taken from the GPU path.
+The runs are too long for the test suite (minutes to hours on one core), so
+their results are stored in compact form:
+
+* ``cube64_re98.8.npz`` -- D3Q19 lid-driven cube, 64^3 nodes, Re = 98.8
+  (lattice Reynolds number 1.57, the value of the 256^3 Re = 400 cube), lid
+  (0.1, 0, 0), 5000 steps: every 4th node per axis of rho and u, the
+  centre-line profile u_x(z) at x = y = 1/2, and the diagnostics.
+* ``cube64_re400.json`` -- the same cube at the literal Re = 400 (lattice
+  Reynolds number 6.35, so the lid itself moves at |u|/e = 1.06): the first
+  step at which the state holds a non-finite value, and max |u|/e every 10
+  steps until then.
+* ``cavity1024_re1000.npz`` -- D2Q9 lid-driven cavity, 1024^2 nodes,
+  Re = 1000, lid 0.1: after 1000, 5000, 20000 and 50000 steps, the
+  diagnostics, the centre-line profiles u_x(y) at x = 1/2 and u_y(x) at
+  y = 1/2 (mean of the two node columns / rows either side of the centre),
+  and every 16th node per axis of rho and u.
+
+Usage: python tests/golden/make_references.py {cube64,cube64_re400,cavity1024}
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_1901_02716_amd import workloads  # noqa: E402
+
+
+def problem(case):
+    p = oracle.Problem(case.q, case.n, case.dx, case.nu, G=tuple(case.G))
+    for face, (rb, ub) in case.fixed.items():
+        p.set_fixed(face, rb, ub)
+    return p
+
+
+def cube64():
+    case = workloads.cavity_3d(n=64, Re=98.8, U=0.1)
+    p = problem(case)
+    t0 = time.time()
+    rho, u = oracle.run(p, case.rho, case.u, 5000)
+    d = oracle.diagnostics(p, rho, u)
+    c = case.n[0] // 2
+    np.savez_compressed(os.path.join(HERE, "cube64_re98.8.npz"), steps=5000, stride=4,
+                        rho=rho[::4, ::4, ::4], u=u[:, ::4, ::4, ::4],
+                        centre_ux=0.5 * (u[0, :, c - 1, c - 1] + u[0, :, c, c]), diagnostics=d,
+                        seconds=time.time() - t0)
+
+
+def cube64_re400():
+    case = workloads.cavity_3d(n=64, Re=400.0, U=0.1)
+    p = problem(case)
+    rho, u = case.rho, case.u
+    blow = None
+    trace = []
+    for step in range(1, 1001):
+        rho, u = oracle.run(p, rho, u, 1)
+        d = oracle.diagnostics(p, rho, u)
+        if step % 10 == 0:
+            trace.append([step, d[5]])
+        if d[6] > 0:
+            blow = step
+            break
+    json.dump({"case": "D3Q19 cube 64^3, Re 400, lid 0.1", "lattice_reynolds": 0.1 * case.dx / case.nu,
+               "lid_mach": 0.1 / oracle.particle_speed(case.nu, case.dx),
+               "first_nonfinite_step": blow, "max_u_over_e_every_10_steps": trace},
+              open(os.path.join(HERE, "cube64_re400.json"), "w"), indent=1)
+
+
+def cavity1024():
+    case = workloads.cavity_2d(n=1024, Re=1000.0, U=0.1)
+    p = problem(case)
+    rho, u = case.rho, case.u
+    out = {}
+    done = 0
+    t0 = time.time()
+    for target in (1000, 5000, 20000, 50000):
+        rho, u = oracle.run(p, rho, u, target - done)
+        done = target
+        d = oracle.diagnostics(p, rho, u)
+        c = case.n[0] // 2
+        out[f"diag_{target}"] = d
+        out[f"ux_centre_{target}"] = 0.5 * (u[0, 0, :, c - 1] + u[0, 0, :, c])
+        out[f"uy_centre_{target}"] = 0.5 * (u[1, 0, c - 1, :] + u[1, 0, c, :])
+        out[f"rho_sub_{target}"] = rho[0, ::16, ::16]
+        out[f"u_sub_{target}"] = u[:, 0, ::16, ::16]
+        out[f"seconds_{target}"] = time.time() - t0
+        np.savez_compressed(os.path.join(HERE, "cavity1024_re1000.npz"), stride=16, **out)
+        print(f"cavity1024: {target} steps after {time.time() - t0:.0f} s", flush=True)
+
+
+if __name__ == "__main__":
+    oracle.build()
+    {"cube64": cube64, "cube64_re400": cube64_re400, "cavity1024": cavity1024}[sys.argv[1]]()

@@ -387,3 +387,52 @@ def test_autotune_does_not_advance_state(precision):
     b.step(7)
     if precision == "fp32":
         assert torch.equal(a.save_state(), b.save_state())
+
+
+# ------------------------------------------------------ D2Q9 fast kernel
+FAST2D = [
+    # walled, ragged width: several segments at W = 1 and W = 2, ragged last segment
+    ("walled_300x77", 300, 77, True, (0.0, 0.0)),
+    # periodic in both axes, width a multiple of 128, with a body force
+    ("periodic_256x50", 256, 50, False, (0.2, -0.1)),
+]
+
+
+def _fast2d_case(nx, ny, walled, G, seed=41):
+    case = workloads.random_field(9, (nx, ny, 1), seed=seed, amp=0.03)
+    if walled:
+        for f in ("xlo", "xhi", "ylo"):
+            case.fixed[f] = (1.0, (0.0, 0.0, 0.0))
+        case.fixed["yhi"] = (1.003, (0.06, 0.0, 0.0))
+    case.G = G + (0.0,)
+    return case
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "s16"])
+@pytest.mark.parametrize("name,nx,ny,walled,G", FAST2D, ids=[f[0] for f in FAST2D])
+def test_fast2d_every_tiling_is_bitwise_identical(name, nx, ny, walled, G, precision):
+    case = _fast2d_case(nx, ny, walled, G)
+    nyo = ny - 2 if walled else ny
+    ref = None
+    for W in (1, 2):
+        for nb in sorted({1, 3, nyo // 2, nyo}):
+            sim = make_sim(case, precision, seed=4)
+            sim.set_tiling(W=W, nzb=nb, kernel="fast2d")
+            t = sim.tiling()
+            assert t["kernel"] == "fast2d" and t["W"] == W and t["nzb"] == nb
+            sim.step(9)
+            st = sim.save_state()
+            if ref is None:
+                ref = st.clone()
+                rho, u = sim.fields()
+                orho, ou = oracle.run(to_problem(case), case.rho, case.u, 9)
+                assert rel_l2(u, ou) < TOL[precision] and rel_l2(rho, orho) < TOL[precision]
+            else:
+                assert torch.equal(st, ref), (W, nb)
+
+
+def test_fast2d_is_the_default_for_cavities():
+    sim = make_sim(workloads.cavity_2d(n=200, Re=50.0, U=0.1), "fp32")
+    assert sim.tiling()["kernel"] == "fast2d"
+    gen = make_sim(workloads.random_field(9, (37, 23, 1), seed=1), "fp32")  # periodic, ragged width
+    assert gen.tiling()["kernel"] == "general"
