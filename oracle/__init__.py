@@ -93,9 +93,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
         lib.oracle_diagnostics.argtypes = [ctypes.POINTER(_Problem), _dp, _dp, _dp]
         lib.oracle_step_at.argtypes = [ctypes.POINTER(_Problem), _dp, _dp, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.c_int64, _dp, _dp]
-        if hasattr(lib, "oracle_adjoint_run"):
-            lib.oracle_adjoint_run.argtypes = [ctypes.POINTER(_Problem), _dp, _dp, ctypes.c_int64,
-                                               _dp, _dp, _dp, _dp]
+        lib.oracle_adjoint_run.argtypes = [ctypes.POINTER(_Problem), _dp, _dp, ctypes.c_int64,
+                                           _dp, _dp, _dp, _dp]
         _libs[path] = lib
     return _libs[path]
 
@@ -222,3 +221,28 @@ def diagnostics(p: Problem, rho: np.ndarray, u: np.ndarray) -> np.ndarray:
     if load().oracle_diagnostics(ctypes.byref(p._c()), _ptr(rho), _ptr(u), _ptr(out)) != 0:
         raise ValueError("invalid problem")
     return out
+
+
+def adjoint_run(p: Problem, rho0: np.ndarray, u0: np.ndarray, steps: int, u_target: np.ndarray):
+    """Loss L = sum (u(T) - u_target)^2 and its gradients (dL/du0, dL/dG).
+
+    u0 and u_target have d planes (physical units); boundary values of fixed
+    faces are imposed on (rho0, u0) first. Returns (loss, grad_u0, grad_G[3]).
+    Keeps the whole trajectory in memory: small problems only.
+    """
+    rho = np.ascontiguousarray(rho0, dtype=np.float64).copy()
+    u = np.ascontiguousarray(u0, dtype=np.float64).copy()
+    tgt = np.ascontiguousarray(u_target, dtype=np.float64)
+    assert rho.size == p.N and u.size == p.d * p.N and tgt.size == p.d * p.N
+    gu = np.zeros_like(u)
+    gG = np.zeros(3)
+    loss = np.zeros(1)
+    L = load()
+    c = p._c()
+    if L.oracle_impose_boundary(ctypes.byref(c), _ptr(rho), _ptr(u)) != 0:
+        raise ValueError("invalid problem")
+    rc = L.oracle_adjoint_run(ctypes.byref(c), _ptr(rho), _ptr(u), int(steps), _ptr(tgt), _ptr(gu), _ptr(gG),
+                              _ptr(loss))
+    if rc != 0:
+        raise ValueError(f"oracle_adjoint_run failed ({rc})")
+    return float(loss[0]), gu, gG

@@ -341,3 +341,128 @@ int oracle_diagnostics(const oracle_problem* p, const double* rho,
   out7[6] = bad;
   return 0;
 }
+
+/* ---- Reverse-mode derivative ---------------------------------------------
+ * Gradient of L = sum_x sum_i (u_i(x, T) - u_target_i(x))^2 (u after `steps`
+ * steps) with respect to the initial velocity u(x, 0) and the body force G,
+ * by the chain rule applied backwards through the steps above, written in
+ * the same physical units:
+ *   m'(x)   = sum_a e_a f_a(x - c_a) + dt G,      u'(x) = m'(x) / rho'(x)
+ *     -> mbar(x) = ubar'(x) / rho'(x),
+ *        rbar_tot(x) = rhobar'(x) - ubar'(x) . u'(x) / rho'(x),
+ *        Gbar += dt sum_x mbar(x)
+ *   rho'(x) = sum_a f_a(x - c_a),  m' = sum_a e_a f_a(x - c_a)
+ *     -> fbar_a(y) = rbar_tot(y + c_a) + e_a . mbar(y + c_a)
+ *   f_a(y)  = w_a rho (1 + 3 e_a.u/e^2 + 9/2 (e_a.u)^2/e^4 - 3/2 u.u/e^2)
+ *     -> rhobar(y) = sum_a fbar_a f_a / rho,
+ *        ubar(y)   = sum_a fbar_a w_a rho (3 e_a/e^2 + 9 (e_a.u) e_a/e^4
+ *                                          - 3 u/e^2)
+ * Fixed nodes hold constants: nothing flows through them (their rbar_tot
+ * and mbar are zero, and their own adjoint is zero).
+ * The whole trajectory is stored (steps + 1 states): for small problems only.
+ * Outputs: grad_u0 (d planes of N), grad_G[3], loss[1]. Returns 0, -1 on an
+ * invalid problem, -2 on allocation failure. */
+int oracle_adjoint_run(const oracle_problem* p, const double* rho0,
+                       const double* u0, int64_t steps,
+                       const double* u_target, double* grad_u0,
+                       double* grad_G, double* loss) {
+  if (validate(p) || steps < 0) return -1;
+  const int q = p->q, d = lattice_dims(q);
+  const int(*c)[3] = lattice_c(q);
+  const double* w = lattice_w(q);
+  const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
+  const int64_t N = nx * ny * nz;
+  const double e = oracle_particle_speed(p->nu, p->dx);
+  const double dt = p->dx / e;
+  const size_t S = (size_t)(N * (d + 1));
+  double* traj = (double*)malloc(sizeof(double) * S * (size_t)(steps + 1));
+  double* rb = (double*)malloc(sizeof(double) * (size_t)N);      /* rhobar */
+  double* ub = (double*)malloc(sizeof(double) * (size_t)(N * d)); /* ubar */
+  double* rt = (double*)malloc(sizeof(double) * (size_t)N);      /* rbar_tot */
+  double* mb = (double*)malloc(sizeof(double) * (size_t)(N * d)); /* mbar */
+  if (!traj || !rb || !ub || !rt || !mb) {
+    free(traj); free(rb); free(ub); free(rt); free(mb);
+    return -2;
+  }
+  /* forward, keeping every state: state n = [rho (N) | u (d N)] */
+  memcpy(traj, rho0, sizeof(double) * (size_t)N);
+  memcpy(traj + N, u0, sizeof(double) * (size_t)(N * d));
+  oracle_impose_boundary(p, traj, traj + N);
+  for (int64_t s = 0; s < steps; ++s) {
+    double* cur = traj + S * (size_t)s;
+    double* nxt = traj + S * (size_t)(s + 1);
+    step_once(p, e, dt, cur, cur + N, nxt, nxt + N);
+  }
+  /* loss and its derivative with respect to the final velocity */
+  const double* fin = traj + S * (size_t)steps;
+  double L = 0.0;
+  for (int64_t x = 0; x < N; ++x) {
+    rb[x] = 0.0;
+    for (int cc = 0; cc < d; ++cc) {
+      double diff = fin[N + cc * N + x] - u_target[cc * N + x];
+      L += diff * diff;
+      ub[cc * N + x] = 2.0 * diff;
+    }
+  }
+  *loss = L;
+  for (int cc = 0; cc < 3; ++cc) grad_G[cc] = 0.0;
+  for (int64_t s = steps - 1; s >= 0; --s) {
+    const double* cur = traj + S * (size_t)s;       /* state n     */
+    const double* nxt = traj + S * (size_t)(s + 1); /* state n + 1 */
+    /* through u' = m' / rho' */
+    for (int64_t k = 0; k < nz; ++k)
+      for (int64_t j = 0; j < ny; ++j)
+        for (int64_t i = 0; i < nx; ++i) {
+          const int64_t x = i + nx * (j + ny * k);
+          if (fixed_face(p, i, j, k) >= 0) {
+            rt[x] = 0.0;
+            for (int cc = 0; cc < d; ++cc) mb[cc * N + x] = 0.0;
+            continue;
+          }
+          double r1 = nxt[x], dot = 0.0;
+          for (int cc = 0; cc < d; ++cc) {
+            mb[cc * N + x] = ub[cc * N + x] / r1;
+            dot += ub[cc * N + x] * nxt[N + cc * N + x];
+            grad_G[cc] += dt * mb[cc * N + x];
+          }
+          rt[x] = rb[x] - dot / r1;
+        }
+    /* through the gather and the equilibrium at the upstream nodes */
+    for (int64_t k = 0; k < nz; ++k)
+      for (int64_t j = 0; j < ny; ++j)
+        for (int64_t i = 0; i < nx; ++i) {
+          const int64_t y = i + nx * (j + ny * k);
+          double rho = cur[y];
+          double uu[3] = {0.0, 0.0, 0.0};
+          for (int cc = 0; cc < d; ++cc) uu[cc] = cur[N + cc * N + y];
+          double rbar = 0.0, ubar[3] = {0.0, 0.0, 0.0};
+          for (int a = 0; a < q; ++a) {
+            int64_t xi = wrap(i + c[a][0], nx);
+            int64_t xj = wrap(j + c[a][1], ny);
+            int64_t xk = wrap(k + c[a][2], nz);
+            int64_t x = xi + nx * (xj + ny * xk);
+            double fbar = rt[x];
+            for (int cc = 0; cc < d; ++cc) fbar += e * (double)c[a][cc] * mb[cc * N + x];
+            double f = oracle_feq(q, a, rho, uu, e);
+            rbar += fbar * f / rho;
+            double eu = 0.0;
+            for (int cc = 0; cc < d; ++cc) eu += e * (double)c[a][cc] * uu[cc];
+            for (int cc = 0; cc < d; ++cc) {
+              double ea = e * (double)c[a][cc];
+              ubar[cc] += fbar * w[a] * rho *
+                          (3.0 * ea / (e * e) + 9.0 * eu * ea / (e * e * e * e) -
+                           3.0 * uu[cc] / (e * e));
+            }
+          }
+          if (fixed_face(p, i, j, k) >= 0) {
+            rbar = 0.0;
+            for (int cc = 0; cc < d; ++cc) ubar[cc] = 0.0;
+          }
+          rb[y] = rbar;
+          for (int cc = 0; cc < d; ++cc) ub[cc * N + y] = ubar[cc];
+        }
+  }
+  memcpy(grad_u0, ub, sizeof(double) * (size_t)(N * d));
+  free(traj); free(rb); free(ub); free(rt); free(mb);
+  return 0;
+}

@@ -28,6 +28,10 @@ MUTANTS = {
     "corner_owner": ("for (int f = 0; f < 6; ++f) {\n    if (p->face_kind[f] != ORACLE_FIXED) continue;",
                      "for (int f = 5; f >= 0; --f) {\n    if (p->face_kind[f] != ORACLE_FIXED) continue;"),
     "energy_half": ("nsum_add(&E, 0.5 * rho[x] * uu);", "nsum_add(&E, rho[x] * uu);"),
+    "adjoint_division_sign": ("rt[x] = rb[x] - dot / r1;", "rt[x] = rb[x] + dot / r1;"),
+    "adjoint_downstream_index": ("int64_t xi = wrap(i + c[a][0], nx);", "int64_t xi = wrap(i - c[a][0], nx);"),
+    "adjoint_force_dt": ("grad_G[cc] += dt * mb[cc * N + x];", "grad_G[cc] += mb[cc * N + x];"),
+    "adjoint_quadratic": ("9.0 * eu * ea / (e * e * e * e)", "4.5 * eu * ea / (e * e * e * e)"),
     "fixed_nodes_updated": ("if (fixed_face(p, i, j, k) >= 0) {\n          /* Recipe step (iv)",
                             "if (fixed_face(p, i, j, k) >= 7) {\n          /* Recipe step (iv)"),
 }
@@ -46,6 +50,9 @@ def _battery():
     yield pins.test_poiseuille_steady_profile_is_exact, {"nu": 0.001, "u0": 0.1}
     yield pins.test_boundary_precedence, {}
     yield pins.test_diagnostics_match_exact_sums, {}
+    yield pins.test_adjoint_matches_central_differences, {"q": 9, "n": (9, 7, 1), "walls": True}
+    yield pins.test_adjoint_matches_central_differences, {"q": 19, "n": (5, 4, 4), "walls": False}
+    yield pins.test_adjoint_force_closed_form, {}
 
 
 def _caught(lib):

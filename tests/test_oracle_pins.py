@@ -388,3 +388,96 @@ def test_step_at_matches_full_step(oracle_lib):
         r, u = oracle.step_at(p, rho0, u0, nodes)
         assert np.array_equal(r, rho1.ravel()[nodes])
         assert np.array_equal(u, u1.reshape(case.d, -1)[:, nodes])
+
+
+# ------------------------------------------------- reverse mode of the step
+
+def _adjoint_case(q, n, walls, seed=17, G=(0.3, -0.2, 0.1)):
+    case = workloads.random_field(q, n, seed=seed)
+    if walls:
+        faces = ("xlo", "xhi", "ylo", "yhi") + (("zlo", "zhi") if q == 19 else ())
+        for f in faces:
+            case.fixed[f] = (1.0, (0.0, 0.0, 0.0))
+        top = "zhi" if q == 19 else "yhi"
+        case.fixed[top] = (1.01, (0.07, 0.0, 0.0))
+    case.G = G
+    tgt = workloads.random_field(q, n, seed=seed + 1).u
+    return case, tgt
+
+
+ADJ_CASES = [(9, (8, 8, 1), False), (9, (9, 7, 1), True), (19, (5, 4, 4), False), (19, (5, 5, 5), True)]
+
+
+@pytest.mark.parametrize("q,n,walls", ADJ_CASES)
+def test_adjoint_matches_central_differences(oracle_lib, q, n, walls):
+    """dL/du0 and dL/dG from the oracle's reverse mode agree with central
+    differences of the oracle's forward loss along random directions."""
+    case, tgt = _adjoint_case(q, n, walls)
+    p = to_problem(case)
+    steps = 7
+    loss, gu, gG = oracle.adjoint_run(p, case.rho, case.u, steps, tgt)
+
+    def L(u0, G):
+        p2 = to_problem(case)
+        p2.G = tuple(G)
+        r, u = oracle.run(p2, case.rho, u0, steps)
+        return float(np.sum((u - tgt) ** 2))
+
+    assert L(case.u, case.G) == pytest.approx(loss, rel=1e-14)
+    rng = np.random.default_rng(5)
+    for _ in range(4):
+        dirn = rng.standard_normal(case.u.shape)
+        # step size balancing truncation (h^2) against cancellation (eps L / h)
+        h = 1e-5 * np.abs(case.u).max()
+        fd = (L(case.u + h * dirn, case.G) - L(case.u - h * dirn, case.G)) / (2 * h)
+        assert np.sum(gu * dirn) == pytest.approx(fd, rel=1e-6, abs=1e-10)
+    for i in range(case.d):
+        dG = np.zeros(3)
+        dG[i] = 1.0
+        h = 1e-4
+        fd = (L(case.u, np.array(case.G) + h * dG) - L(case.u, np.array(case.G) - h * dG)) / (2 * h)
+        assert gG[i] == pytest.approx(fd, rel=1e-6, abs=1e-10)
+
+
+@pytest.mark.parametrize("q,n,walls", ADJ_CASES)
+def test_adjoint_matches_torch_autograd(oracle_lib, q, n, walls):
+    """The same gradients taped by PyTorch (float64) through an independent
+    torch.roll implementation of the step."""
+    import torch
+    import torch_ref
+
+    case, tgt = _adjoint_case(q, n, walls)
+    p = to_problem(case)
+    rho0 = case.rho.copy()
+    u0 = case.u.copy()
+    oracle.impose_boundary(p, rho0, u0)
+    steps = 9
+    loss, gu, gG = oracle.adjoint_run(p, case.rho, case.u, steps, tgt)
+    e = oracle.particle_speed(case.nu, case.dx)
+    ut = torch.tensor(u0, requires_grad=True)
+    G = torch.tensor(np.array(case.G, dtype=np.float64), requires_grad=True)
+    Lt = torch_ref.run_loss(q, torch.tensor(rho0), ut, G, e, case.dx / e, steps, torch.tensor(tgt),
+                            fixed_mask=_mask(case))
+    Lt.backward()
+    assert Lt.item() == pytest.approx(loss, rel=1e-13)
+    gt = ut.grad.numpy().copy()
+    gt[:, _mask(case)] = 0.0  # fixed nodes: their initial values are replaced by the boundary values
+    assert np.abs(gu - gt).max() < 1e-12 * max(1.0, np.abs(gt).max())
+    assert np.allclose(gG[:case.d], G.grad.numpy()[:case.d], rtol=1e-12, atol=1e-14)
+
+
+def test_adjoint_force_closed_form(oracle_lib):
+    """A unidirectional periodic shear flow with a force along it stays
+    unidirectional with rho = 1, and u_x(T) = e S^T (u0/e) + T dt G_x with the
+    mean-preserving smoother S, so for a zero target dL/dG_x =
+    2 T dt sum_x u_x(T)."""
+    q, n, m, steps = 9, 16, 2, 12
+    case = workloads.shear_wave(q, n, m, 0.05)
+    case.G = (0.7, 0.0, 0.0)
+    p = to_problem(case)
+    tgt = np.zeros_like(case.u)
+    loss, gu, gG = oracle.adjoint_run(p, case.rho, case.u, steps, tgt)
+    r, u = oracle.run(p, case.rho, case.u, steps)
+    dt = oracle.time_step(case.nu, case.dx)
+    assert gG[0] == pytest.approx(2 * steps * dt * u[0].sum(), rel=1e-12)
+    assert abs(gG[1]) < 1e-12
