@@ -176,6 +176,42 @@ int maclab_set_tiling(maclab_t h, int kernel, int W, int nyb, int nzb, int pf);
  * per step. Synchronises. */
 int maclab_autotune(maclab_t h, int reps, double* best_ms);
 
+/* Replaces the uniform body force G (physical units) for subsequent steps. */
+int maclab_set_body_force(maclab_t h, const double* G);
+
+/* One step from the native state at src to dst (both caller-owned device
+ * buffers of maclab_state_bytes; dst receives the fixed-face values too),
+ * with the rounding stream of step `step_index`. The handle's own state and
+ * step counter are untouched. Used to recompute a trajectory segment from a
+ * checkpoint. */
+int maclab_step_external(maclab_t h, const void* src, void* dst, int64_t step_index);
+
+/* Reverse mode. An adjoint vector holds the derivative of a loss with
+ * respect to the stored state (rho, u~ = u / e) in maclab_adjoint_bytes:
+ * d+1 planes (density, then the velocity components) of the handle's plane
+ * stride, in FP64 for MACLAB_FP64 storage and FP32 otherwise. Device memory,
+ * caller-owned.
+ *  seed:   adj = adjoint of the state for a loss whose derivative with
+ *          respect to the physical velocity is dLdu (device FP64, d*N,
+ *          SoA like the fields); the density part is zero.
+ *  reset:  zeroes the FP64 accumulator of the body-force derivative.
+ *  step:   given the states at steps n and n+1 (native, as saved) and the
+ *          adjoint at n+1, writes the adjoint at n (chain rule through
+ *          Eqs. (2), (4), (5) and the body-force term; fixed nodes carry
+ *          nothing) and adds this step's contribution to the force
+ *          accumulator. adj_np1 and adj_n must differ.
+ *  result: from the adjoint at step 0 writes dL/du0 (device FP64, d*N) and,
+ *          if dLdrho0 is not NULL, dL/drho0 (device FP64, N); dLdG (host,
+ *          may be NULL) receives dL/dG from the accumulator. Synchronises
+ *          when dLdG is requested.
+ * The force accumulator is summed per workgroup in FP64 in a fixed order,
+ * so results are reproducible. */
+size_t maclab_adjoint_bytes(maclab_t h);
+int maclab_adjoint_seed(maclab_t h, const double* dLdu, void* adj);
+int maclab_adjoint_reset(maclab_t h);
+int maclab_adjoint_step(maclab_t h, const void* state_n, const void* state_np1, const void* adj_np1, void* adj_n);
+int maclab_adjoint_result(maclab_t h, const void* adj0, double* dLdu0, double* dLdrho0, double dLdG[3]);
+
 /* Releases the handle (not the caller's memory). NULL is ignored. */
 void maclab_destroy(maclab_t h);
 

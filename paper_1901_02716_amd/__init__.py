@@ -15,4 +15,8 @@ def __getattr__(name):
         from .simulation import Simulation
 
         return Simulation
+    if name == "rollout":
+        from .adjoint import rollout
+
+        return rollout
     raise AttributeError(name)

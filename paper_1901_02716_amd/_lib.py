@@ -18,7 +18,9 @@ SYMBOLS = (
     "maclab_workspace_bytes", "maclab_init", "maclab_set_bc", "maclab_set_fields", "maclab_step",
     "maclab_step_checked", "maclab_get_fields", "maclab_diagnostics", "maclab_params",
     "maclab_state_bytes", "maclab_save_state", "maclab_load_state", "maclab_get_tiling",
-    "maclab_set_tiling", "maclab_autotune", "maclab_destroy", "maclab_last_error",
+    "maclab_set_tiling", "maclab_autotune", "maclab_set_body_force", "maclab_step_external",
+    "maclab_adjoint_bytes", "maclab_adjoint_seed", "maclab_adjoint_reset", "maclab_adjoint_step",
+    "maclab_adjoint_result", "maclab_destroy", "maclab_last_error",
 )
 
 
@@ -75,6 +77,14 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.maclab_get_tiling.argtypes = [H, ctypes.POINTER(ctypes.c_int)]
     lib.maclab_set_tiling.argtypes = [H, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.maclab_autotune.argtypes = [H, ctypes.c_int, dp]
+    lib.maclab_set_body_force.argtypes = [H, dp]
+    lib.maclab_step_external.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+    lib.maclab_adjoint_bytes.restype = ctypes.c_size_t
+    lib.maclab_adjoint_bytes.argtypes = [H]
+    lib.maclab_adjoint_seed.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p]
+    lib.maclab_adjoint_reset.argtypes = [H]
+    lib.maclab_adjoint_step.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.maclab_adjoint_result.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, dp]
     lib.maclab_destroy.restype = None
     lib.maclab_destroy.argtypes = [H]
     lib.maclab_last_error.restype = ctypes.c_char_p

@@ -27,6 +27,7 @@ struct Layout {
   size_t state_bytes = 0;     // (d + 1) planes
   size_t partial_bytes = 0;   // reduction partials
   size_t staging_bytes = 0;   // host transfer staging
+  size_t adjoint_bytes = 0;   // per-workgroup FP64 slots of the force adjoint (+ fold result)
   size_t workspace_bytes = 0;
 };
 
@@ -64,6 +65,15 @@ FastShape fast_default_shape(const Layout& L, const StepParams& p, int cus);
 int fast_candidates(const Layout& L, const StepParams& p, int cus, FastShape* out, int max_out);
 hipError_t launch_step_fast(const Layout& L, const void* src, void* dst, const StepParams& p, const FastShape& sh,
                             hipStream_t s);
+
+// Reverse mode (kernels_adjoint.hip).
+int64_t adjoint_slots(const Layout& L);
+hipError_t launch_adjoint_step(const Layout& L, const void* sn, const void* sn1, const void* an1, void* an,
+                               const StepParams& p, double* gslots, hipStream_t s);
+hipError_t launch_adjoint_seed(const Layout& L, const double* dLdu, void* adj, double e, hipStream_t s);
+hipError_t launch_adjoint_result(const Layout& L, const void* adj, double* dLdu, double* dLdrho, double e,
+                                 hipStream_t s);
+hipError_t launch_adjoint_fold(const double* slots, int64_t nslots, double* out, hipStream_t s);
 
 // Fast D2Q9 path (kernels_2d.hip): one wavefront per (x-segment of 64*kx
 // nodes, band of rows); nband bands per segment.

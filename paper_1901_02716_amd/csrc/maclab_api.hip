@@ -33,6 +33,7 @@ struct maclab_s {
   double* partials = nullptr;
   double* result = nullptr;  // kDiagValues doubles after the partials
   char* staging = nullptr;
+  double* gslots = nullptr;  // force-adjoint slots (adjoint_slots(L) x 4), then 4 doubles of fold result
   FaceValues fv;
   double e = 0, dt = 0;
   int64_t steps = 0;
@@ -125,7 +126,9 @@ int make_layout(const maclab_config* c, Layout* L, std::string* why) {
   L->state_bytes = (size_t)(d + 1) * (size_t)L->plane * (size_t)L->bytes;
   L->partial_bytes = round_up(sizeof(double) * (kDiagBlocks + 1) * kDiagValues, kAlign);
   L->staging_bytes = std::min(kStagingMax, round_up(sizeof(double) * (size_t)N, kAlign));
-  L->workspace_bytes = 2 * round_up(L->state_bytes, kAlign) + L->partial_bytes + L->staging_bytes;
+  L->adjoint_bytes = round_up(sizeof(double) * 4 * (size_t)(adjoint_slots(*L) + 1), kAlign);
+  L->workspace_bytes =
+      2 * round_up(L->state_bytes, kAlign) + L->partial_bytes + L->staging_bytes + L->adjoint_bytes;
   return MACLAB_OK;
 }
 
@@ -265,6 +268,7 @@ int maclab_init(const maclab_config* cfg, maclab_t* out) {
   h->partials = (double*)(ws + 2 * sb);
   h->result = h->partials + (size_t)kDiagBlocks * kDiagValues;
   h->staging = ws + 2 * sb + L.partial_bytes;
+  h->gslots = (double*)(ws + 2 * sb + L.partial_bytes + L.staging_bytes);
   for (int f = 0; f < 6; ++f) {
     h->fv.kind[f] = MACLAB_BC_PERIODIC;
     h->fv.rho[f] = cfg->rho_ref;
@@ -533,6 +537,78 @@ int maclab_autotune(maclab_t h, int reps, double* best_ms) {
   h->plan = cand[best_i];
   h->plan_set = true;
   if (best_ms) *best_ms = best;
+  return MACLAB_OK;
+}
+
+int maclab_set_body_force(maclab_t h, const double* G) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!G) return fail(h, MACLAB_EINVAL, "G is NULL");
+  for (int c = 0; c < 3; ++c)
+    if (!isfinite(G[c])) return fail(h, MACLAB_EINVAL, "body force must be finite");
+  for (int c = 0; c < 3; ++c) h->cfg.body_force[c] = G[c];
+  return MACLAB_OK;
+}
+
+int maclab_step_external(maclab_t h, const void* src, void* dst, int64_t step_index) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!src || !dst || src == dst) return fail(h, MACLAB_EINVAL, "src and dst must be distinct device buffers");
+  int rc = check_faces(h);
+  if (rc) return rc;
+  StepParams p = make_params(h);
+  p.step = (uint64_t)step_index;
+  p.sr_key = sr_key(p.seed, p.step);
+  const Plan pl = current_plan(h, p);
+  HIP_TRY(h, launch_plan(h->L, p, pl, src, dst, h->stream));
+  bool any_fixed = false;
+  for (int f = 0; f < 6; ++f) any_fixed |= h->fv.kind[f] == MACLAB_BC_FIXED;
+  if (any_fixed) HIP_TRY(h, launch_impose_bc(h->L, dst, dst, h->fv, h->cfg.rho_ref, h->e, h->stream));
+  return MACLAB_OK;
+}
+
+size_t maclab_adjoint_bytes(maclab_t h) {
+  if (!h) return 0;
+  const size_t t = h->L.precision == MACLAB_FP64 ? sizeof(double) : sizeof(float);
+  return (size_t)(h->L.d + 1) * (size_t)h->L.plane * t;
+}
+
+int maclab_adjoint_seed(maclab_t h, const double* dLdu, void* adj) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!dLdu || !adj) return fail(h, MACLAB_EINVAL, "dLdu and adj must be device pointers");
+  HIP_TRY(h, launch_adjoint_seed(h->L, dLdu, adj, h->e, h->stream));
+  return MACLAB_OK;
+}
+
+int maclab_adjoint_reset(maclab_t h) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  HIP_TRY(h, hipMemsetAsync(h->gslots, 0, h->L.adjoint_bytes, h->stream));
+  return MACLAB_OK;
+}
+
+int maclab_adjoint_step(maclab_t h, const void* state_n, const void* state_np1, const void* adj_np1, void* adj_n) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!state_n || !state_np1 || !adj_np1 || !adj_n || adj_np1 == adj_n)
+    return fail(h, MACLAB_EINVAL, "state and adjoint buffers must be device pointers, adj_np1 != adj_n");
+  int rc = check_faces(h);
+  if (rc) return rc;
+  StepParams p = make_params(h);
+  HIP_TRY(h, launch_adjoint_step(h->L, state_n, state_np1, adj_np1, adj_n, p, h->gslots, h->stream));
+  return MACLAB_OK;
+}
+
+int maclab_adjoint_result(maclab_t h, const void* adj0, double* dLdu0, double* dLdrho0, double dLdG[3]) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!adj0) return fail(h, MACLAB_EINVAL, "adj0 is NULL");
+  if (dLdu0) HIP_TRY(h, launch_adjoint_result(h->L, adj0, dLdu0, dLdrho0, h->e, h->stream));
+  if (dLdG) {
+    const int64_t ns = adjoint_slots(h->L);
+    double* fold = h->gslots + 4 * ns;
+    HIP_TRY(h, launch_adjoint_fold(h->gslots, ns, fold, h->stream));
+    double g[4];
+    HIP_TRY(h, hipMemcpyAsync(g, fold, sizeof(double) * 4, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    // g = dt G / e per step, so dL/dG = (dt / e) sum_steps sum_x Mbar
+    for (int c = 0; c < 3; ++c) dLdG[c] = c < h->L.d ? g[c] * h->dt / h->e : 0.0;
+  }
   return MACLAB_OK;
 }
 

@@ -81,9 +81,10 @@ class Simulation:
 
     def set_fields(self, rho, u) -> None:
         """rho: N values, u: d*N values (physical units), numpy or torch."""
-        if isinstance(rho, torch.Tensor) and rho.is_cuda:
-            r = rho.to(self.device, torch.float64).contiguous()
-            v = u.to(self.device, torch.float64).contiguous()
+        on_dev = any(isinstance(a, torch.Tensor) and a.is_cuda for a in (rho, u))
+        if on_dev:
+            r = torch.as_tensor(rho).to(self.device, torch.float64).contiguous()
+            v = torch.as_tensor(u).to(self.device, torch.float64).contiguous()
             assert r.numel() == self.N and v.numel() == self.d * self.N
             _lib.check(self.lib.maclab_set_fields(self.h, r.data_ptr(), v.data_ptr(), 1), self.h)
             torch.cuda.current_stream(self.device).synchronize()
@@ -150,6 +151,47 @@ class Simulation:
         best = ctypes.c_double(0.0)
         _lib.check(self.lib.maclab_autotune(self.h, int(reps), ctypes.byref(best)), self.h)
         return best.value
+
+    # ------------------------------------------------------- reverse mode
+    def set_body_force(self, G) -> None:
+        g = (ctypes.c_double * 3)(*[float(v) for v in (tuple(G) + (0.0, 0.0, 0.0))[:3]])
+        _lib.check(self.lib.maclab_set_body_force(self.h, g), self.h)
+
+    def step_external(self, src: torch.Tensor, dst: torch.Tensor, step_index: int) -> None:
+        """One step from the native state in `src` to `dst` (device buffers of
+        state_bytes()); the simulation's own state does not change."""
+        _lib.check(self.lib.maclab_step_external(self.h, src.data_ptr(), dst.data_ptr(), int(step_index)), self.h)
+
+    def adjoint_bytes(self) -> int:
+        return int(self.lib.maclab_adjoint_bytes(self.h))
+
+    def new_adjoint(self) -> torch.Tensor:
+        return torch.empty(self.adjoint_bytes(), dtype=torch.uint8, device=self.device)
+
+    def adjoint_seed(self, dLdu: torch.Tensor, adj: torch.Tensor) -> None:
+        g = dLdu.to(self.device, torch.float64).contiguous()
+        assert g.numel() == self.d * self.N
+        _lib.check(self.lib.maclab_adjoint_seed(self.h, g.data_ptr(), adj.data_ptr()), self.h)
+        self._keep = g  # alive until the stream has consumed it
+
+    def adjoint_reset(self) -> None:
+        _lib.check(self.lib.maclab_adjoint_reset(self.h), self.h)
+
+    def adjoint_step(self, state_n, state_np1, adj_np1, adj_n) -> None:
+        _lib.check(self.lib.maclab_adjoint_step(self.h, state_n.data_ptr(), state_np1.data_ptr(),
+                                                adj_np1.data_ptr(), adj_n.data_ptr()), self.h)
+
+    def adjoint_result(self, adj0: torch.Tensor, want_rho: bool = False):
+        """(dL/du0 as (d, nz, ny, nx) float64 device tensor, dL/dG as 3 floats
+        [, dL/drho0])."""
+        shape = (self.n[2], self.n[1], self.n[0])
+        gu = torch.empty((self.d,) + shape, dtype=torch.float64, device=self.device)
+        gr = torch.empty(shape, dtype=torch.float64, device=self.device) if want_rho else None
+        gG = np.zeros(3)
+        _lib.check(self.lib.maclab_adjoint_result(self.h, adj0.data_ptr(), gu.data_ptr(),
+                                                  gr.data_ptr() if gr is not None else None,
+                                                  gG.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self.h)
+        return (gu, gG, gr) if want_rho else (gu, gG)
 
     # ---------------------------------------------------------- checkpoint
     def state_bytes(self) -> int:

@@ -213,3 +213,21 @@ def batch_draw(count: int = 512, seed: int = 4, nmin: int = 64, nmax: int = 512,
         U = float(rng.uniform(u_min, u_max))
         out.append((N, Re, U))
     return out
+
+
+def adjoint_directions(n: int = 512, count_u: int = 16, count_G: int = 16, seed: int = 3):
+    """Seeded unit directions for directional-derivative checks of the
+    adjoint: `count_u` fields of shape (2, 1, n, n) with unit Euclidean norm
+    over all components, then `count_G` unit vectors in the (G_x, G_y) plane
+    (returned as 3-vectors)."""
+    rng = np.random.default_rng(seed)
+    du = []
+    for _ in range(count_u):
+        v = rng.standard_normal((2, 1, n, n))
+        du.append(v / np.linalg.norm(v))
+    dG = []
+    for _ in range(count_G):
+        g = rng.standard_normal(2)
+        g /= np.linalg.norm(g)
+        dG.append(np.array([g[0], g[1], 0.0]))
+    return du, dG

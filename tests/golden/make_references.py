@@ -19,7 +19,13 @@ their results are stored in compact form:
   y = 1/2 (mean of the two node columns / rows either side of the centre),
   and every 16th node per axis of rho and u.
 
-Usage: python tests/golden/make_references.py {cube64,cube64_re400,cavity1024}
+* ``adjoint512_fd.json`` -- D2Q9 periodic 512^2 box, nu = 0.005, initial
+  velocity a sum of 8 random Fourier modes (seed 1), target the same
+  construction with seed 2, G = 0, 2000 steps, loss sum (u(T) - u_target)^2:
+  the loss and central differences (h = 1e-4) of it along 16 unit
+  directions in u0 and 16 in G (seed 3).
+
+Usage: python tests/golden/make_references.py {cube64,cube64_re400,cavity1024,adjoint512 [workers]}
 """
 from __future__ import annotations
 
@@ -100,6 +106,42 @@ def cavity1024():
         print(f"cavity1024: {target} steps after {time.time() - t0:.0f} s", flush=True)
 
 
+def _loss(args):
+    which, k, sign = args
+    case, tgt = workloads.adjoint_case()
+    du, dG = workloads.adjoint_directions()
+    h = 1e-4
+    u0 = case.u.copy()
+    G = np.zeros(3)
+    if which == "u":
+        u0 = u0 + sign * h * du[k]
+    elif which == "G":
+        G = G + sign * h * dG[k]
+    case.G = tuple(G)
+    p = problem(case)
+    rho, u = oracle.run(p, case.rho, u0, case.steps)
+    return args, float(np.sum((u - tgt) ** 2))
+
+
+def adjoint512(workers=6):
+    from multiprocessing import Pool
+
+    jobs = [("base", 0, 0)] + [(w, k, s) for w in ("u", "G") for k in range(16) for s in (1, -1)]
+    t0 = time.time()
+    with Pool(workers) as pool:
+        res = dict(pool.map(_loss, jobs))
+    h = 1e-4
+    out = {"case": "D2Q9 periodic 512^2, nu 0.005, 2000 steps, modes seed 1, target seed 2, G = 0",
+           "h": h, "loss": res[("base", 0, 0)],
+           "fd_u": [(res[("u", k, 1)] - res[("u", k, -1)]) / (2 * h) for k in range(16)],
+           "fd_G": [(res[("G", k, 1)] - res[("G", k, -1)]) / (2 * h) for k in range(16)],
+           "seconds": time.time() - t0}
+    json.dump(out, open(os.path.join(HERE, "adjoint512_fd.json"), "w"), indent=1)
+
+
 if __name__ == "__main__":
     oracle.build()
-    {"cube64": cube64, "cube64_re400": cube64_re400, "cavity1024": cavity1024}[sys.argv[1]]()
+    if sys.argv[1] == "adjoint512":
+        adjoint512(int(sys.argv[2]) if len(sys.argv) > 2 else 6)
+    else:
+        {"cube64": cube64, "cube64_re400": cube64_re400, "cavity1024": cavity1024}[sys.argv[1]]()
