@@ -186,31 +186,55 @@ int maclab_set_body_force(maclab_t h, const double* G);
  * checkpoint. */
 int maclab_step_external(maclab_t h, const void* src, void* dst, int64_t step_index);
 
-/* Reverse mode. An adjoint vector holds the derivative of a loss with
- * respect to the stored state (rho, u~ = u / e) in maclab_adjoint_bytes:
- * d+1 planes (density, then the velocity components) of the handle's plane
- * stride, in FP64 for MACLAB_FP64 storage and FP32 otherwise. Device memory,
- * caller-owned.
- *  seed:   adj = adjoint of the state for a loss whose derivative with
- *          respect to the physical velocity is dLdu (device FP64, d*N,
- *          SoA like the fields); the density part is zero.
- *  reset:  zeroes the FP64 accumulator of the body-force derivative.
- *  step:   given the states at steps n and n+1 (native, as saved) and the
- *          adjoint at n+1, writes the adjoint at n (chain rule through
- *          Eqs. (2), (4), (5) and the body-force term; fixed nodes carry
- *          nothing) and adds this step's contribution to the force
- *          accumulator. adj_np1 and adj_n must differ.
- *  result: from the adjoint at step 0 writes dL/du0 (device FP64, d*N) and,
- *          if dLdrho0 is not NULL, dL/drho0 (device FP64, N); dLdG (host,
- *          may be NULL) receives dL/dG from the accumulator. Synchronises
- *          when dLdG is requested.
- * The force accumulator is summed per workgroup in FP64 in a fixed order,
- * so results are reproducible. */
+/* Reverse mode (the chain rule through Eqs. (2), (4), (5) and the
+ * body-force term of test 2, for a loss L on later velocities). An adjoint
+ * vector is caller-owned device memory of maclab_adjoint_bytes: d+1 planes
+ * of the handle's plane stride, FP64 for MACLAB_FP64 storage and FP32
+ * otherwise. For the state at step n it holds not (dL/drho, dL/du~) but the
+ * pair the reverse step needs, Mbar = (dL/du~) / rho and Rbar = dL/drho -
+ * Mbar . u~ (zero at fixed nodes, whose values do not depend on the past).
+ *  seed:    from the native state at the last step T (as saved) and the
+ *           derivative dLdu of the loss with respect to the physical
+ *           velocity at T (device FP64, d*N, SoA like the fields), writes
+ *           the adjoint at T.
+ *  reset:   zeroes the FP64 accumulator of the body-force derivative.
+ *  step:    from the state at step n and the adjoint at n+1, writes the
+ *           adjoint at n and adds step n+1's force contribution to the
+ *           accumulator. adj_np1 and adj_n must differ.
+ *  segment: the reverse sweep over steps step_index .. step_index+nsteps-1
+ *           from a checkpoint: recomputes the states at step_index+1 ..
+ *           step_index+nsteps-1 from `ckpt` (the state at step_index) into
+ *           `states` (nsteps-1 consecutive slots of maclab_state_bytes;
+ *           NULL when nsteps = 1), then applies `step` nsteps times, ping-
+ *           ponging between adj_a and adj_b: on entry adj[*which] (adj_a for
+ *           0, adj_b for 1) holds the adjoint at step_index+nsteps, on
+ *           return adj[*which] holds the adjoint at step_index.
+ *  result:  from the state and the adjoint at step 0 writes dL/du0 (device
+ *           FP64, d*N) and, if dLdrho0 is not NULL, dL/drho0 (device FP64,
+ *           N); dLdG (host, may be NULL) receives dL/dG from the
+ *           accumulator. Synchronises when dLdG is requested.
+ * The force accumulator is summed per wavefront or workgroup in FP64 into
+ * slots each owned by one of them, folded in a fixed order, so results are
+ * reproducible. Stream-ordered; every buffer must stay valid until the
+ * stream reaches the call. */
 size_t maclab_adjoint_bytes(maclab_t h);
-int maclab_adjoint_seed(maclab_t h, const double* dLdu, void* adj);
+int maclab_adjoint_seed(maclab_t h, const void* state_T, const double* dLdu, void* adj);
 int maclab_adjoint_reset(maclab_t h);
-int maclab_adjoint_step(maclab_t h, const void* state_n, const void* state_np1, const void* adj_np1, void* adj_n);
-int maclab_adjoint_result(maclab_t h, const void* adj0, double* dLdu0, double* dLdrho0, double dLdG[3]);
+int maclab_adjoint_step(maclab_t h, const void* state_n, const void* adj_np1, void* adj_n);
+int maclab_adjoint_segment(maclab_t h, const void* ckpt, void* states, int64_t nsteps, int64_t step_index,
+                           void* adj_a, void* adj_b, int* which);
+int maclab_adjoint_result(maclab_t h, const void* state0, const void* adj0, double* dLdu0, double* dLdrho0,
+                          double dLdG[3]);
+
+/* Kernel of the reverse step. kernel -1: automatic (the default); 0: the
+ * general kernel (any lattice); 3: the fast D2Q9 kernel (walled x of any
+ * extent, or periodic x whose extent is a multiple of 64*kx): one
+ * wavefront per (x-segment of 64*kx nodes, kx in {1,2}, band of rows),
+ * 1 <= nband <= ceil(ny/4). get writes {kernel, kx, nband} of the kernel
+ * the reverse step uses. EUNSUPPORTED when kernel 3 does not handle the
+ * lattice, EINVAL for an invalid tiling. */
+int maclab_set_adjoint_tiling(maclab_t h, int kernel, int kx, int nband);
+int maclab_get_adjoint_tiling(maclab_t h, int out[3]);
 
 /* Releases the handle (not the caller's memory). NULL is ignored. */
 void maclab_destroy(maclab_t h);

@@ -20,7 +20,8 @@ SYMBOLS = (
     "maclab_state_bytes", "maclab_save_state", "maclab_load_state", "maclab_get_tiling",
     "maclab_set_tiling", "maclab_autotune", "maclab_set_body_force", "maclab_step_external",
     "maclab_adjoint_bytes", "maclab_adjoint_seed", "maclab_adjoint_reset", "maclab_adjoint_step",
-    "maclab_adjoint_result", "maclab_destroy", "maclab_last_error",
+    "maclab_adjoint_segment", "maclab_adjoint_result", "maclab_set_adjoint_tiling",
+    "maclab_get_adjoint_tiling", "maclab_destroy", "maclab_last_error",
 )
 
 
@@ -81,10 +82,15 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.maclab_step_external.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
     lib.maclab_adjoint_bytes.restype = ctypes.c_size_t
     lib.maclab_adjoint_bytes.argtypes = [H]
-    lib.maclab_adjoint_seed.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p]
+    vp = ctypes.c_void_p
+    lib.maclab_adjoint_seed.argtypes = [H, vp, vp, vp]
     lib.maclab_adjoint_reset.argtypes = [H]
-    lib.maclab_adjoint_step.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
-    lib.maclab_adjoint_result.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, dp]
+    lib.maclab_adjoint_step.argtypes = [H, vp, vp, vp]
+    lib.maclab_adjoint_segment.argtypes = [H, vp, vp, ctypes.c_int64, ctypes.c_int64, vp, vp,
+                                           ctypes.POINTER(ctypes.c_int)]
+    lib.maclab_adjoint_result.argtypes = [H, vp, vp, vp, vp, dp]
+    lib.maclab_set_adjoint_tiling.argtypes = [H, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.maclab_get_adjoint_tiling.argtypes = [H, ctypes.POINTER(ctypes.c_int)]
     lib.maclab_destroy.restype = None
     lib.maclab_destroy.argtypes = [H]
     lib.maclab_last_error.restype = ctypes.c_char_p

@@ -3,11 +3,12 @@ forward and adjoint steps with square-root checkpointing.
 
 ``rollout(sim, rho0, u0, G, steps)`` returns the physical velocity after
 ``steps`` steps; its backward gives dL/du0 and dL/dG. The forward keeps the
-native state every K = ceil(sqrt(steps)) steps; the backward recomputes one
-segment at a time from its checkpoint into K + 1 state buffers
-(maclab_step_external) and walks the adjoint back through it
-(maclab_adjoint_step). Memory: about 2 sqrt(steps) states. All arithmetic
-runs in the library's HIP kernels; torch only holds buffers.
+native state every K = ceil(sqrt(steps)) steps; the backward walks the
+segments in reverse with one library call each (maclab_adjoint_segment),
+which recomputes the segment's states from its checkpoint into K - 1 state
+slots and runs the reverse steps through them. Memory: about 2 sqrt(steps)
+states. All arithmetic runs in the library's HIP kernels; torch only holds
+buffers.
 """
 from __future__ import annotations
 
@@ -29,6 +30,7 @@ class _Rollout(torch.autograd.Function):
             n = min(K, steps - done)
             sim.step(n)
             done += n
+        ctx.final = sim.save_state()
         _, uT = sim.fields(on_device=True)
         ctx.sim, ctx.ckpts, ctx.steps, ctx.K, ctx.step0 = sim, ckpts, steps, K, step0
         ctx.u_shape = u0.shape
@@ -39,21 +41,17 @@ class _Rollout(torch.autograd.Function):
     def backward(ctx, grad_uT):
         sim, ckpts, steps, K, step0 = ctx.sim, ctx.ckpts, ctx.steps, ctx.K, ctx.step0
         adj = [sim.new_adjoint(), sim.new_adjoint()]
-        sim.adjoint_seed(grad_uT, adj[0])
+        sim.adjoint_seed(ctx.final, grad_uT, adj[0])
         sim.adjoint_reset()
-        buf = [torch.empty(sim.state_bytes(), dtype=torch.uint8, device=sim.device) for _ in range(K + 1)]
-        cur = 0
+        states = sim.new_states(K - 1) if K > 1 else None
+        which = 0
         for seg in reversed(range(len(ckpts))):
             n0 = seg * K
             n1 = min(n0 + K, steps)
-            buf[0].copy_(ckpts[seg])
-            for j in range(n1 - n0):
-                sim.step_external(buf[j], buf[j + 1], step0 + n0 + j)
-            for j in reversed(range(n1 - n0)):
-                sim.adjoint_step(buf[j], buf[j + 1], adj[cur], adj[cur ^ 1])
-                cur ^= 1
-        gu, gG = sim.adjoint_result(adj[cur])
-        return gu.reshape(ctx.u_shape), torch.tensor(gG, dtype=torch.float64, device=ctx.G_device), None, None, None, None
+            which = sim.adjoint_segment(ckpts[seg], states, n1 - n0, step0 + n0, adj, which)
+        gu, gG = sim.adjoint_result(ckpts[0], adj[which])
+        return (gu.reshape(ctx.u_shape), torch.tensor(gG, dtype=torch.float64, device=ctx.G_device),
+                None, None, None, None)
 
 
 def rollout(sim, rho0, u0: torch.Tensor, G: torch.Tensor, steps: int, checkpoint_every: int | None = None):

@@ -66,15 +66,6 @@ int fast_candidates(const Layout& L, const StepParams& p, int cus, FastShape* ou
 hipError_t launch_step_fast(const Layout& L, const void* src, void* dst, const StepParams& p, const FastShape& sh,
                             hipStream_t s);
 
-// Reverse mode (kernels_adjoint.hip).
-int64_t adjoint_slots(const Layout& L);
-hipError_t launch_adjoint_step(const Layout& L, const void* sn, const void* sn1, const void* an1, void* an,
-                               const StepParams& p, double* gslots, hipStream_t s);
-hipError_t launch_adjoint_seed(const Layout& L, const double* dLdu, void* adj, double e, hipStream_t s);
-hipError_t launch_adjoint_result(const Layout& L, const void* adj, double* dLdu, double* dLdrho, double e,
-                                 hipStream_t s);
-hipError_t launch_adjoint_fold(const double* slots, int64_t nslots, double* out, hipStream_t s);
-
 // Fast D2Q9 path (kernels_2d.hip): one wavefront per (x-segment of 64*kx
 // nodes, band of rows); nband bands per segment.
 struct Fast2DShape {
@@ -86,5 +77,22 @@ Fast2DShape fast2d_default_shape(const Layout& L, const StepParams& p, int cus);
 int fast2d_candidates(const Layout& L, const StepParams& p, int cus, Fast2DShape* out, int max_out);
 hipError_t launch_step_fast2d(const Layout& L, const void* src, void* dst, const StepParams& p,
                               const Fast2DShape& sh, hipStream_t s);
+
+// Reverse mode (kernels_adjoint.hip). Adjoint buffers hold (Rbar, Mbar) in
+// the compute type, d + 1 planes of `plane` elements.
+int64_t adjoint_slots(const Layout& L);
+hipError_t launch_adjoint_step(const Layout& L, const void* sn, const void* an1, void* an, const StepParams& p,
+                               double* gslots, hipStream_t s);
+bool adjoint2d_supported(const Layout& L, const StepParams& p);
+bool adjoint2d_shape_valid(const Layout& L, const StepParams& p, const Fast2DShape& sh);
+Fast2DShape adjoint2d_default_shape(const Layout& L, const StepParams& p, int cus);
+hipError_t launch_adjoint_fast2d(const Layout& L, const void* sn, const void* an1, void* an, const StepParams& p,
+                                 const Fast2DShape& sh, double* gslots, hipStream_t s);
+hipError_t launch_adjoint_seed(const Layout& L, const void* sT, const double* dLdu, void* adj, const StepParams& p,
+                               double e, hipStream_t s);
+hipError_t launch_adjoint_result(const Layout& L, const void* s0, const void* adj, double* dLdu, double* dLdrho,
+                                 double rho_ref, double e, hipStream_t s);
+hipError_t launch_adjoint_fold(const double* slots, int64_t nslots, double* out, hipStream_t s);
+hipError_t launch_zero_doubles(double* dst, int64_t count, hipStream_t s);
 
 }  // namespace maclab

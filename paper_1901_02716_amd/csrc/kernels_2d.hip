@@ -83,23 +83,6 @@ struct RowAcc2 {
   T r[KX], mx[KX], my[KX];  // 36 * (drho', m')
 };
 
-__device__ __forceinline__ float dpp_from_left(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x13C, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float dpp_from_right(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xF, 0xF, false));
-}
-__device__ __forceinline__ double dpp_from_left(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) & 0xffffffff), 0x13C, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) >> 32), 0x13C, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double dpp_from_right(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) & 0xffffffff), 0x134, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) >> 32), 0x134, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 // Wavefronts per SIMD the register budget must allow (keeps the scheduler
 // from spending registers on hoisting).
 template <class C, int KX>

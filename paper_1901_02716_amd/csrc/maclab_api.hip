@@ -40,6 +40,8 @@ struct maclab_s {
   int cus = 256;               // compute units of the device
   Plan plan;                   // kernel and tiling of the step
   bool plan_set = false;       // chosen by maclab_set_tiling / maclab_autotune
+  int adj_kernel = -1;         // reverse step: -1 automatic, 0 general, 3 fast D2Q9
+  Fast2DShape adj2;            // its tiling when set explicitly
   std::string err;
 };
 
@@ -571,34 +573,124 @@ size_t maclab_adjoint_bytes(maclab_t h) {
   return (size_t)(h->L.d + 1) * (size_t)h->L.plane * t;
 }
 
-int maclab_adjoint_seed(maclab_t h, const double* dLdu, void* adj) {
+int maclab_adjoint_seed(maclab_t h, const void* state_T, const double* dLdu, void* adj) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
-  if (!dLdu || !adj) return fail(h, MACLAB_EINVAL, "dLdu and adj must be device pointers");
-  HIP_TRY(h, launch_adjoint_seed(h->L, dLdu, adj, h->e, h->stream));
+  if (!state_T || !dLdu || !adj) return fail(h, MACLAB_EINVAL, "state_T, dLdu and adj must be device pointers");
+  int rc = check_faces(h);
+  if (rc) return rc;
+  const StepParams p = make_params(h);
+  HIP_TRY(h, launch_adjoint_seed(h->L, state_T, dLdu, adj, p, h->e, h->stream));
   return MACLAB_OK;
 }
 
 int maclab_adjoint_reset(maclab_t h) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
-  HIP_TRY(h, hipMemsetAsync(h->gslots, 0, h->L.adjoint_bytes, h->stream));
+  HIP_TRY(h, launch_zero_doubles(h->gslots, (int64_t)(h->L.adjoint_bytes / sizeof(double)), h->stream));
   return MACLAB_OK;
 }
 
-int maclab_adjoint_step(maclab_t h, const void* state_n, const void* state_np1, const void* adj_np1, void* adj_n) {
+namespace {
+// The reverse step's kernel: the fast D2Q9 one where it applies.
+bool adjoint_fast2d(maclab_t h, const StepParams& p, Fast2DShape* sh) {
+  if (h->adj_kernel == 0 || !adjoint2d_supported(h->L, p)) return false;
+  *sh = h->adj_kernel == 3 ? h->adj2 : adjoint2d_default_shape(h->L, p, h->cus);
+  return adjoint2d_shape_valid(h->L, p, *sh);
+}
+
+int adjoint_one(maclab_t h, const StepParams& p, const void* state_n, const void* adj_np1, void* adj_n) {
+  Fast2DShape sh;
+  if (adjoint_fast2d(h, p, &sh))
+    HIP_TRY(h, launch_adjoint_fast2d(h->L, state_n, adj_np1, adj_n, p, sh, h->gslots, h->stream));
+  else
+    HIP_TRY(h, launch_adjoint_step(h->L, state_n, adj_np1, adj_n, p, h->gslots, h->stream));
+  return MACLAB_OK;
+}
+}  // namespace
+
+int maclab_set_adjoint_tiling(maclab_t h, int kernel, int kx, int nband) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
-  if (!state_n || !state_np1 || !adj_np1 || !adj_n || adj_np1 == adj_n)
+  if (kernel == -1 || kernel == 0) {
+    h->adj_kernel = kernel;
+    return MACLAB_OK;
+  }
+  if (kernel != 3) return fail(h, MACLAB_EINVAL, "adjoint kernel must be -1, 0 or 3");
+  const StepParams p = make_params(h);
+  if (!adjoint2d_supported(h->L, p)) return fail(h, MACLAB_EUNSUPPORTED, "the fast D2Q9 adjoint does not handle this lattice");
+  Fast2DShape sh;
+  sh.kx = kx;
+  sh.nband = nband;
+  if (!adjoint2d_shape_valid(h->L, p, sh))
+    return fail(h, MACLAB_EINVAL, "invalid adjoint tiling kx=%d nband=%d (kx in {1,2}, 1 <= nband <= ceil(ny/4))", kx,
+                nband);
+  h->adj_kernel = 3;
+  h->adj2 = sh;
+  return MACLAB_OK;
+}
+
+int maclab_get_adjoint_tiling(maclab_t h, int out[3]) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!out) return fail(h, MACLAB_EINVAL, "out is NULL");
+  const StepParams p = make_params(h);
+  Fast2DShape sh;
+  if (adjoint_fast2d(h, p, &sh)) {
+    out[0] = 3;
+    out[1] = sh.kx;
+    out[2] = sh.nband;
+  } else {
+    out[0] = 0;
+    out[1] = out[2] = 0;
+  }
+  return MACLAB_OK;
+}
+
+int maclab_adjoint_step(maclab_t h, const void* state_n, const void* adj_np1, void* adj_n) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!state_n || !adj_np1 || !adj_n || adj_np1 == adj_n)
     return fail(h, MACLAB_EINVAL, "state and adjoint buffers must be device pointers, adj_np1 != adj_n");
   int rc = check_faces(h);
   if (rc) return rc;
-  StepParams p = make_params(h);
-  HIP_TRY(h, launch_adjoint_step(h->L, state_n, state_np1, adj_np1, adj_n, p, h->gslots, h->stream));
+  const StepParams p = make_params(h);
+  return adjoint_one(h, p, state_n, adj_np1, adj_n);
+}
+
+int maclab_adjoint_segment(maclab_t h, const void* ckpt, void* states, int64_t nsteps, int64_t step_index,
+                           void* adj_a, void* adj_b, int* which) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!ckpt || !adj_a || !adj_b || !which || adj_a == adj_b || (*which != 0 && *which != 1))
+    return fail(h, MACLAB_EINVAL, "ckpt, adj_a, adj_b (distinct) and which (0 or 1) are required");
+  if (nsteps < 1 || step_index < 0) return fail(h, MACLAB_EINVAL, "nsteps must be >= 1 and step_index >= 0");
+  if (nsteps > 1 && !states) return fail(h, MACLAB_EINVAL, "states is NULL");
+  int rc = check_faces(h);
+  if (rc) return rc;
+  const size_t sb = h->L.state_bytes;
+  auto slot = [&](int64_t n) -> const void* {  // state at step step_index + n
+    return n == 0 ? ckpt : (const void*)((const char*)states + (size_t)(n - 1) * sb);
+  };
+  // recompute the states after the checkpoint
+  for (int64_t n = 1; n < nsteps; ++n) {
+    rc = maclab_step_external(h, slot(n - 1), (void*)slot(n), step_index + n - 1);
+    if (rc) return rc;
+  }
+  void* adj[2] = {adj_a, adj_b};
+  int cur = *which;
+  const StepParams p = make_params(h);
+  for (int64_t n = nsteps - 1; n >= 0; --n) {
+    rc = adjoint_one(h, p, slot(n), adj[cur], adj[cur ^ 1]);
+    if (rc) return rc;
+    cur ^= 1;
+  }
+  *which = cur;
   return MACLAB_OK;
 }
 
-int maclab_adjoint_result(maclab_t h, const void* adj0, double* dLdu0, double* dLdrho0, double dLdG[3]) {
+int maclab_adjoint_result(maclab_t h, const void* state0, const void* adj0, double* dLdu0, double* dLdrho0,
+                          double dLdG[3]) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
   if (!adj0) return fail(h, MACLAB_EINVAL, "adj0 is NULL");
-  if (dLdu0) HIP_TRY(h, launch_adjoint_result(h->L, adj0, dLdu0, dLdrho0, h->e, h->stream));
+  if (dLdu0) {
+    if (!state0) return fail(h, MACLAB_EINVAL, "state0 is NULL");
+    HIP_TRY(h, launch_adjoint_result(h->L, state0, adj0, dLdu0, dLdrho0, h->cfg.rho_ref, h->e, h->stream));
+  }
   if (dLdG) {
     const int64_t ns = adjoint_slots(h->L);
     double* fold = h->gslots + 4 * ns;

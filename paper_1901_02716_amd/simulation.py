@@ -168,30 +168,55 @@ class Simulation:
     def new_adjoint(self) -> torch.Tensor:
         return torch.empty(self.adjoint_bytes(), dtype=torch.uint8, device=self.device)
 
-    def adjoint_seed(self, dLdu: torch.Tensor, adj: torch.Tensor) -> None:
+    def new_states(self, count: int) -> torch.Tensor:
+        """`count` consecutive native state slots (for adjoint_segment)."""
+        return torch.empty(max(count, 1) * self.state_bytes(), dtype=torch.uint8, device=self.device)
+
+    def adjoint_seed(self, state_T: torch.Tensor, dLdu: torch.Tensor, adj: torch.Tensor) -> None:
+        """Adjoint at the last step T from its native state and dL/du(T)."""
         g = dLdu.to(self.device, torch.float64).contiguous()
         assert g.numel() == self.d * self.N
-        _lib.check(self.lib.maclab_adjoint_seed(self.h, g.data_ptr(), adj.data_ptr()), self.h)
+        _lib.check(self.lib.maclab_adjoint_seed(self.h, state_T.data_ptr(), g.data_ptr(), adj.data_ptr()), self.h)
         self._keep = g  # alive until the stream has consumed it
 
     def adjoint_reset(self) -> None:
         _lib.check(self.lib.maclab_adjoint_reset(self.h), self.h)
 
-    def adjoint_step(self, state_n, state_np1, adj_np1, adj_n) -> None:
-        _lib.check(self.lib.maclab_adjoint_step(self.h, state_n.data_ptr(), state_np1.data_ptr(),
-                                                adj_np1.data_ptr(), adj_n.data_ptr()), self.h)
+    def adjoint_step(self, state_n, adj_np1, adj_n) -> None:
+        _lib.check(self.lib.maclab_adjoint_step(self.h, state_n.data_ptr(), adj_np1.data_ptr(),
+                                                adj_n.data_ptr()), self.h)
 
-    def adjoint_result(self, adj0: torch.Tensor, want_rho: bool = False):
+    def adjoint_segment(self, ckpt, states, nsteps: int, step_index: int, adj, which: int) -> int:
+        """Reverse sweep over steps step_index .. step_index+nsteps-1 from the
+        checkpoint `ckpt`; adj is a pair of adjoint buffers, adj[which] holding
+        the adjoint at step_index+nsteps. Returns the index of the buffer that
+        holds the adjoint at step_index."""
+        w = ctypes.c_int(int(which))
+        sp = states.data_ptr() if states is not None else None
+        _lib.check(self.lib.maclab_adjoint_segment(self.h, ckpt.data_ptr(), sp, int(nsteps), int(step_index),
+                                                   adj[0].data_ptr(), adj[1].data_ptr(), ctypes.byref(w)), self.h)
+        return w.value
+
+    def adjoint_result(self, state0: torch.Tensor, adj0: torch.Tensor, want_rho: bool = False):
         """(dL/du0 as (d, nz, ny, nx) float64 device tensor, dL/dG as 3 floats
         [, dL/drho0])."""
         shape = (self.n[2], self.n[1], self.n[0])
         gu = torch.empty((self.d,) + shape, dtype=torch.float64, device=self.device)
         gr = torch.empty(shape, dtype=torch.float64, device=self.device) if want_rho else None
         gG = np.zeros(3)
-        _lib.check(self.lib.maclab_adjoint_result(self.h, adj0.data_ptr(), gu.data_ptr(),
+        _lib.check(self.lib.maclab_adjoint_result(self.h, state0.data_ptr(), adj0.data_ptr(), gu.data_ptr(),
                                                   gr.data_ptr() if gr is not None else None,
                                                   gG.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self.h)
         return (gu, gG, gr) if want_rho else (gu, gG)
+
+    def set_adjoint_tiling(self, kernel: str = "auto", kx: int = 0, nband: int = 0) -> None:
+        k = {"auto": -1, "general": 0, "fast2d": 3}[kernel]
+        _lib.check(self.lib.maclab_set_adjoint_tiling(self.h, k, int(kx), int(nband)), self.h)
+
+    def adjoint_tiling(self) -> dict:
+        out = (ctypes.c_int * 3)()
+        _lib.check(self.lib.maclab_get_adjoint_tiling(self.h, out), self.h)
+        return {"kernel": {0: "general", 3: "fast2d"}[out[0]], "kx": out[1], "nband": out[2]}
 
     # ---------------------------------------------------------- checkpoint
     def state_bytes(self) -> int:

@@ -84,18 +84,36 @@ def cube64_re400():
               open(os.path.join(HERE, "cube64_re400.json"), "w"), indent=1)
 
 
-def cavity1024():
+def cavity1024(resume=None):
+    """Long run; the full state is saved every 2500 steps to `resume` (a
+    scratch file outside the repository) so an interrupted run continues."""
+    import tempfile
+
+    resume = resume or os.path.join(tempfile.gettempdir(), "maclab_cavity1024_state.npz")
     case = workloads.cavity_2d(n=1024, Re=1000.0, U=0.1)
     p = problem(case)
     rho, u = case.rho, case.u
     out = {}
     done = 0
-    t0 = time.time()
+    elapsed = 0.0
+    if os.path.exists(resume):
+        z = np.load(resume)
+        rho, u, done, elapsed = z["rho"], z["u"], int(z["done"]), float(z["elapsed"])
+        out = {k[4:]: z[k] for k in z.files if k.startswith("out_")}
+        print(f"cavity1024: resuming at step {done}", flush=True)
+    t0 = time.time() - elapsed
+    c = case.n[0] // 2
     for target in (1000, 5000, 20000, 50000):
-        rho, u = oracle.run(p, rho, u, target - done)
-        done = target
+        while done < target:
+            n = min(2500, target - done)
+            rho, u = oracle.run(p, rho, u, n)
+            done += n
+            if done < target:
+                np.savez(resume, rho=rho, u=u, done=done, elapsed=time.time() - t0,
+                         **{"out_" + k: v for k, v in out.items()})
+        if f"diag_{target}" in out:
+            continue
         d = oracle.diagnostics(p, rho, u)
-        c = case.n[0] // 2
         out[f"diag_{target}"] = d
         out[f"ux_centre_{target}"] = 0.5 * (u[0, 0, :, c - 1] + u[0, 0, :, c])
         out[f"uy_centre_{target}"] = 0.5 * (u[1, 0, c - 1, :] + u[1, 0, c, :])
@@ -103,6 +121,8 @@ def cavity1024():
         out[f"u_sub_{target}"] = u[:, 0, ::16, ::16]
         out[f"seconds_{target}"] = time.time() - t0
         np.savez_compressed(os.path.join(HERE, "cavity1024_re1000.npz"), stride=16, **out)
+        np.savez(resume, rho=rho, u=u, done=done, elapsed=time.time() - t0,
+                 **{"out_" + k: v for k, v in out.items()})
         print(f"cavity1024: {target} steps after {time.time() - t0:.0f} s", flush=True)
 
 

@@ -16,7 +16,7 @@ import pytest
 import torch
 
 import oracle
-from paper_1901_02716_amd import Simulation, rollout, workloads
+from paper_1901_02716_amd import MaclabError, Simulation, rollout, workloads
 from conftest import rel_l2, to_problem
 
 pytestmark = pytest.mark.gpu
@@ -128,17 +128,87 @@ def test_adjoint_result_rho_and_zero_seed():
     case, _ = _case(9, (16, 12, 1), True)
     sim = _sim(case, "fp64")
     sim.set_fields(case.rho, case.u)
-    adj = sim.new_adjoint()
-    sim.adjoint_seed(torch.zeros((2, 1, 12, 16), dtype=torch.float64), adj)
-    sim.adjoint_reset()
     s0 = sim.save_state()
     s1 = torch.empty_like(s0)
     sim.step_external(s0, s1, 0)
+    adj = sim.new_adjoint()
+    sim.adjoint_seed(s1, torch.zeros((2, 1, 12, 16), dtype=torch.float64), adj)
+    sim.adjoint_reset()
     adj2 = sim.new_adjoint()
-    sim.adjoint_step(s0, s1, adj, adj2)
-    gu, gG, gr = sim.adjoint_result(adj2, want_rho=True)
+    sim.adjoint_step(s0, adj, adj2)
+    gu, gG, gr = sim.adjoint_result(s0, adj2, want_rho=True)
     assert torch.count_nonzero(gu).item() == 0 and torch.count_nonzero(gr).item() == 0
     assert np.all(gG == 0.0)
+
+
+def test_adjoint_rho_gradient_matches_oracle_fd():
+    """dL/drho0 from the result call against central differences of the
+    oracle's loss in the initial density."""
+    case, tgt = _case(9, (64, 20, 1), True)
+    steps = 5
+    sim = _sim(case, "fp64")
+    sim.set_fields(case.rho, case.u)
+    ckpts = [sim.save_state()]
+    sim.step(steps)
+    final = sim.save_state()
+    _, uT = sim.fields()
+    dLdu = torch.tensor(2.0 * (uT - tgt))
+    adj = [sim.new_adjoint(), sim.new_adjoint()]
+    sim.adjoint_seed(final, dLdu, adj[0])
+    sim.adjoint_reset()
+    w = sim.adjoint_segment(ckpts[0], sim.new_states(steps - 1), steps, 0, adj, 0)
+    _, _, gr = sim.adjoint_result(ckpts[0], adj[w], want_rho=True)
+    gr = gr.cpu().numpy()
+    p = to_problem(case)
+
+    def L(rho0):
+        _, u = oracle.run(p, rho0, case.u, steps)
+        return float(np.sum((u - tgt) ** 2))
+
+    rng = np.random.default_rng(9)
+    for _ in range(3):
+        dirn = rng.standard_normal(case.rho.shape)
+        h = 1e-6
+        fd = (L(case.rho + h * dirn) - L(case.rho - h * dirn)) / (2 * h)
+        assert np.sum(gr * dirn) == pytest.approx(fd, rel=1e-6)
+
+
+@pytest.mark.parametrize("q,n,walls", [(9, (64, 48, 1), False), (9, (128, 40, 1), True), (9, (77, 29, 1), True),
+                                       (9, (256, 16, 1), False)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fast_adjoint_matches_general(q, n, walls, precision):
+    """The fast D2Q9 reverse step, at every tiling, against the general one."""
+    case, tgt = _case(q, n, walls)
+    steps = 6
+    sim = _sim(case, precision)
+    sim.set_adjoint_tiling("general")
+    _, gu_ref, gG_ref = _grads(sim, case, tgt, steps)
+    tol = 1e-13 if precision == "fp64" else 1e-6
+    shapes = [(1, 1), (1, 3), (2, 2), (2, (n[1] + 3) // 4)]
+    for kx, nb in shapes:
+        if not walls and n[0] % (64 * kx):
+            continue
+        sim.set_adjoint_tiling("fast2d", kx, nb)
+        assert sim.adjoint_tiling() == {"kernel": "fast2d", "kx": kx, "nband": nb}
+        _, gu, gG = _grads(sim, case, tgt, steps)
+        print(f"  kx={kx} nband={nb} relL2 {rel_l2(gu, gu_ref):.2e} gG {gG} vs {gG_ref}", flush=True)
+        assert rel_l2(gu, gu_ref) < tol
+        assert np.allclose(gG, gG_ref, rtol=tol, atol=tol * np.abs(gG_ref).max())
+
+
+def test_adjoint_tiling_validation():
+    case, _ = _case(9, (64, 20, 1), False)
+    sim = _sim(case, "fp32")
+    assert sim.adjoint_tiling()["kernel"] == "fast2d"
+    with pytest.raises(MaclabError):
+        sim.set_adjoint_tiling("fast2d", 2, 1)  # periodic x of 64 nodes: kx = 1 only
+    with pytest.raises(MaclabError):
+        sim.set_adjoint_tiling("fast2d", 1, 6)  # more bands than ceil(ny / 4)
+    c3, _ = _case(19, (8, 8, 8), False)
+    s3 = _sim(c3, "fp32")
+    assert s3.adjoint_tiling()["kernel"] == "general"
+    with pytest.raises(MaclabError):
+        s3.set_adjoint_tiling("fast2d", 1, 1)
 
 
 def test_step_external_matches_step():
