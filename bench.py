@@ -90,6 +90,77 @@ def time_variant(case, precision, steps, warmup, autotune=True, tiling=None):
     return ms / steps, wall, d
 
 
+def time_adjoint(T: int, precision: str = "fp32", reps: int = 3):
+    """Reverse-mode cost on the periodic D2Q9 512^2 box (nu = 0.005, Fourier-
+    mode initial field and target): the backward of a T-step rollout with
+    sqrt(T) checkpointing (recompute + reverse steps) against T forward steps.
+    Also the bare reverse-step kernel against the bare forward kernel."""
+    import math
+
+    import torch
+
+    from paper_1901_02716_amd import Simulation, rollout, workloads
+
+    case, tgt = workloads.adjoint_case(steps=T)
+    sim = Simulation(9, case.n, case.dx, case.nu, precision=precision)
+    dev = sim.device
+    tg = torch.tensor(tgt, device=dev)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def fwd_ms(n):
+        sim.set_fields(case.rho, case.u)
+        sim.step(10)
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record(sim.stream)
+        sim.step(n)
+        b.record(sim.stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    fwd_ms(T)  # warm-up
+    fwd = min(fwd_ms(T) for _ in range(reps)) / T
+    bwd = []
+    for _ in range(reps):
+        u0 = torch.tensor(case.u, device=dev, requires_grad=True)
+        G = torch.zeros(3, dtype=torch.float64, requires_grad=True)
+        uT = rollout(sim, case.rho, u0, G, T)
+        loss = ((uT - tg) ** 2).sum()
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record(sim.stream)
+        t0 = time.perf_counter()
+        loss.backward()
+        b.record(sim.stream)
+        torch.cuda.synchronize()
+        bwd.append(max(a.elapsed_time(b), (time.perf_counter() - t0) * 1e3))
+    # bare kernels: the reverse step alone on resident buffers
+    sim.set_fields(case.rho, case.u)
+    s0 = sim.save_state()
+    adj = [sim.new_adjoint(), sim.new_adjoint()]
+    sim.adjoint_seed(s0, torch.zeros_like(tg), adj[0])
+    sim.adjoint_reset()
+    n = 500
+    for i in range(20):
+        sim.adjoint_step(s0, adj[i & 1], adj[(i & 1) ^ 1])
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record(sim.stream)
+    for i in range(n):
+        sim.adjoint_step(s0, adj[i & 1], adj[(i & 1) ^ 1])
+    b.record(sim.stream)
+    torch.cuda.synchronize()
+    adj_kernel = a.elapsed_time(b) / n
+    bwd_ms = min(bwd)
+    out = {"workload": f"D2Q9 periodic 512^2 nu=0.005 T={T} {precision}, K={math.ceil(math.sqrt(T))}",
+           "forward_ms_per_step": round(fwd, 5), "backward_ms": round(bwd_ms, 3),
+           "backward_over_T_forward": round(bwd_ms / (T * fwd), 3),
+           "reverse_step_ms": round(adj_kernel, 5), "reverse_over_forward_step": round(adj_kernel / fwd, 3),
+           "adjoint_tiling": sim.adjoint_tiling(), "forward_tiling": sim.tiling()}
+    sim.close()
+    return out
+
+
 def cpu_baseline(case, steps: int):
     """The FP64 oracle on `steps` steps of the same lattice, one thread."""
     import oracle
@@ -131,6 +202,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="use the default tiling")
     ap.add_argument("--tiling", default="", help="W,nyb,nzb,pf[,kernel] of the fast kernel (skips autotuning)")
+    ap.add_argument("--adjoint-steps", type=int, default=2000,
+                    help="T of the reverse-mode cost measurement (0 to skip)")
     ap.add_argument("--profile-copy-mib", type=int, default=0,
                     help="after timing, run one torch copy of this many MiB (counter calibration)")
     args = ap.parse_args(argv)
@@ -168,6 +241,8 @@ def main(argv=None):
                        "vs_" + args.precision: round(vm / mlups, 3),
                        "hbm_frac": round(2 * (d + 1) * BYTES[v] * lu / (vms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
+    adjoint = time_adjoint(args.adjoint_steps) if args.adjoint_steps > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         cm, cdt = cpu_baseline(case, args.cpu_steps)
@@ -202,6 +277,7 @@ def main(argv=None):
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "cpu_baseline": cpu,
         "variants": variants,
+        "adjoint": adjoint,
         "diagnostics_after": {"mass": diag[0], "max_u_over_e": diag[5], "nonfinite": diag[6]},
         "wall_s": round(wall, 3),
         "kernel_source_hash": kernel_source_hash(),
