@@ -236,6 +236,54 @@ int maclab_adjoint_result(maclab_t h, const void* state0, const void* adj0, doub
 int maclab_set_adjoint_tiling(maclab_t h, int kernel, int kx, int nband);
 int maclab_get_adjoint_tiling(maclab_t h, int out[3]);
 
+/* ----------------------------------------------------------------- batch
+ * Many independent D2Q9 lattices (for instance lid-driven cavities of
+ * different sizes and Reynolds numbers, test 3 of the paper) advanced
+ * together. Each lattice is described by its own maclab_config (lattice
+ * must be MACLAB_D2Q9; precision, rho_ref, seed and stream must match those
+ * of lattice 0; the workspace fields are ignored) and lives in one caller-
+ * owned workspace of maclab_batch_workspace_bytes (256-byte aligned device
+ * memory; 0 means an invalid description).
+ *  lattice:       a handle for lattice `index`, owned by the batch (NULL if
+ *                 out of range). Use it with maclab_set_bc, set_fields,
+ *                 get_fields, diagnostics, params, save_state and load_state
+ *                 like a handle of its own; maclab_destroy ignores it and
+ *                 reverse mode returns MACLAB_EUNSUPPORTED. Those calls share
+ *                 the batch's scratch, so they must not overlap in time.
+ *  step:          n steps of every lattice (Eqs. (4)-(5) with each
+ *                 lattice's faces and force): one launch per step over a
+ *                 table of work items {lattice, x-segment of 64*kx nodes,
+ *                 band of `rows` rows}, largest first. Runs of
+ *                 steps_per_graph steps are captured once in a HIP graph
+ *                 and replayed on a private stream ordered after and before
+ *                 the caller's stream (not for MACLAB_S16, whose rounding is
+ *                 keyed per step). Results are bitwise those of stepping each
+ *                 lattice with maclab_step on the fast D2Q9 kernel.
+ *                 MACLAB_EINVAL if a lattice was stepped on its own.
+ *  step_separate: the same n steps as one launch per lattice per step (the
+ *                 schedule a loop over single lattices would use).
+ *  get_tiling:    out[3] = {kx, rows, work items}. set_tiling: kx in {1,2},
+ *                 rows >= 4 (a periodic x extent must be a multiple of
+ *                 64*kx). autotune: times every candidate (each launched
+ *                 `reps` times into the spare buffers, so nothing advances),
+ *                 keeps the fastest; *best_ms (may be NULL) gets its time per
+ *                 step. set_graph: steps per captured graph, even, 0 for none
+ *                 (default 32). */
+typedef struct maclab_batch_s* maclab_batch_t;
+size_t maclab_batch_workspace_bytes(const maclab_config* cfgs, int count);
+int maclab_batch_init(const maclab_config* cfgs, int count, void* workspace, size_t workspace_bytes,
+                      maclab_batch_t* out);
+maclab_t maclab_batch_lattice(maclab_batch_t b, int index);
+int maclab_batch_count(maclab_batch_t b);
+int maclab_batch_step(maclab_batch_t b, int64_t n);
+int maclab_batch_step_separate(maclab_batch_t b, int64_t n);
+int maclab_batch_get_tiling(maclab_batch_t b, int out[3]);
+int maclab_batch_set_tiling(maclab_batch_t b, int kx, int rows);
+int maclab_batch_set_graph(maclab_batch_t b, int steps_per_graph);
+int maclab_batch_autotune(maclab_batch_t b, int reps, double* best_ms);
+void maclab_batch_destroy(maclab_batch_t b);
+const char* maclab_batch_last_error(maclab_batch_t b);
+
 /* Releases the handle (not the caller's memory). NULL is ignored. */
 void maclab_destroy(maclab_t h);
 

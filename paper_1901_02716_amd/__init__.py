@@ -15,6 +15,10 @@ def __getattr__(name):
         from .simulation import Simulation
 
         return Simulation
+    if name in ("Batch", "cavities"):
+        from . import batch
+
+        return getattr(batch, name)
     if name == "rollout":
         from .adjoint import rollout
 

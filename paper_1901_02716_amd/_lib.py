@@ -21,7 +21,10 @@ SYMBOLS = (
     "maclab_set_tiling", "maclab_autotune", "maclab_set_body_force", "maclab_step_external",
     "maclab_adjoint_bytes", "maclab_adjoint_seed", "maclab_adjoint_reset", "maclab_adjoint_step",
     "maclab_adjoint_segment", "maclab_adjoint_result", "maclab_set_adjoint_tiling",
-    "maclab_get_adjoint_tiling", "maclab_destroy", "maclab_last_error",
+    "maclab_get_adjoint_tiling", "maclab_batch_workspace_bytes", "maclab_batch_init", "maclab_batch_lattice",
+    "maclab_batch_count", "maclab_batch_step", "maclab_batch_step_separate", "maclab_batch_get_tiling",
+    "maclab_batch_set_tiling", "maclab_batch_set_graph", "maclab_batch_autotune", "maclab_batch_destroy",
+    "maclab_batch_last_error", "maclab_destroy", "maclab_last_error",
 )
 
 
@@ -91,6 +94,22 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.maclab_adjoint_result.argtypes = [H, vp, vp, vp, vp, dp]
     lib.maclab_set_adjoint_tiling.argtypes = [H, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.maclab_get_adjoint_tiling.argtypes = [H, ctypes.POINTER(ctypes.c_int)]
+    lib.maclab_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.maclab_batch_workspace_bytes.argtypes = [ctypes.POINTER(Config), ctypes.c_int]
+    lib.maclab_batch_init.argtypes = [ctypes.POINTER(Config), ctypes.c_int, vp, ctypes.c_size_t, ctypes.POINTER(H)]
+    lib.maclab_batch_lattice.restype = H
+    lib.maclab_batch_lattice.argtypes = [H, ctypes.c_int]
+    lib.maclab_batch_count.argtypes = [H]
+    lib.maclab_batch_step.argtypes = [H, ctypes.c_int64]
+    lib.maclab_batch_step_separate.argtypes = [H, ctypes.c_int64]
+    lib.maclab_batch_get_tiling.argtypes = [H, ctypes.POINTER(ctypes.c_int)]
+    lib.maclab_batch_set_tiling.argtypes = [H, ctypes.c_int, ctypes.c_int]
+    lib.maclab_batch_set_graph.argtypes = [H, ctypes.c_int]
+    lib.maclab_batch_autotune.argtypes = [H, ctypes.c_int, dp]
+    lib.maclab_batch_destroy.argtypes = [H]
+    lib.maclab_batch_destroy.restype = None
+    lib.maclab_batch_last_error.restype = ctypes.c_char_p
+    lib.maclab_batch_last_error.argtypes = [H]
     lib.maclab_destroy.restype = None
     lib.maclab_destroy.argtypes = [H]
     lib.maclab_last_error.restype = ctypes.c_char_p
@@ -98,6 +117,12 @@ def load(path: str | None = None) -> ctypes.CDLL:
     if path is None:
         _lib = lib
     return lib
+
+
+def check_batch(rc: int, batch=None) -> None:
+    if rc != OK:
+        msg = load().maclab_batch_last_error(batch)
+        raise MaclabError(rc, msg.decode() if msg else "")
 
 
 def check(rc: int, handle=None) -> None:

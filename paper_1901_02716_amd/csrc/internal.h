@@ -78,6 +78,21 @@ int fast2d_candidates(const Layout& L, const StepParams& p, int cus, Fast2DShape
 hipError_t launch_step_fast2d(const Layout& L, const void* src, void* dst, const StepParams& p,
                               const Fast2DShape& sh, hipStream_t s);
 
+// Where one lattice of a batch lives in memory and how its boundaries behave
+// (elements relative to the batch's state buffer).
+struct Lattice2D {
+  int nx, ny, pitch;  // node counts; elements between rows (>= nx)
+  int xper, yper;     // periodic axes (else both faces fixed)
+  int aligned;        // rows start on a KX-element boundary (vector loads)
+  double gx, gy;      // dt G / e
+  int64_t base;       // element offset of the lattice's first field plane
+  int64_t plane;      // elements between field planes
+};
+// A batch step: work item {lattice, x0, y0, y1} of a device table, one
+// wavefront each, all lattices in one launch.
+hipError_t launch_step_fast2d_items(int precision, int kx, const void* src, void* dst, const Lattice2D* lat,
+                                    const int4* items, int nitems, double rho_ref, uint32_t sr_key, hipStream_t s);
+
 // Reverse mode (kernels_adjoint.hip). Adjoint buffers hold (Rbar, Mbar) in
 // the compute type, d + 1 planes of `plane` elements.
 int64_t adjoint_slots(const Layout& L);

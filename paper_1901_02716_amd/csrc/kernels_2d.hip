@@ -20,16 +20,6 @@
 
 namespace maclab {
 
-// Where a lattice lives in memory and how its boundaries behave.
-struct Lattice2D {
-  int nx, ny, pitch;  // node counts; elements between rows (>= nx)
-  int xper, yper;     // periodic axes (else both faces fixed)
-  int aligned;        // rows start on a KX-element boundary (vector loads)
-  double gx, gy;      // dt G / e
-  int64_t base;       // element offset of the lattice's first field plane
-  int64_t plane;      // elements between field planes
-};
-
 struct Fast2DParams {
   const Lattice2D* lat;  // device array (batch) ...
   Lattice2D one;         // ... or this single lattice when lat == nullptr
@@ -242,7 +232,7 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src,
         const T vx = __builtin_fma(am.mx[q], (T)(1.0 / 36.0), (T)lt.gx) * inv;
         const T vy = __builtin_fma(am.my[q], (T)(1.0 / 36.0), (T)lt.gy) * inv;
         uint32_t bits = 0;
-        if constexpr (needs_rng<C>::value) bits = sr_node_bits(p.sr_key, lt.base + rb + xb + q);
+        if constexpr (needs_rng<C>::value) bits = sr_node_bits(p.sr_key, rb + xb + q);  // lattice-local node index
         o0.v[q] = C::enc(drn, 0, bits);
         o1.v[q] = C::enc(vx, 1, bits);
         o2.v[q] = C::enc(vy, 2, bits);
@@ -355,6 +345,20 @@ static hipError_t launch2d(int precision, int kx, const void* src, void* dst, co
     case MACLAB_S16: return launch2d_codec<CodecS16>(kx, src, dst, fp, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_step_fast2d_items(int precision, int kx, const void* src, void* dst, const Lattice2D* lat,
+                                    const int4* items, int nitems, double rho_ref, uint32_t sr_key, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  Fast2DParams fp{};
+  fp.lat = lat;
+  fp.items = items;
+  fp.nitems = nitems;
+  fp.nseg = 1;
+  fp.nband = 1;
+  fp.rho_ref = rho_ref;
+  fp.sr_key = sr_key;
+  return launch2d(precision, kx, src, dst, fp, s);
 }
 
 hipError_t launch_step_fast2d(const Layout& L, const void* src, void* dst, const StepParams& p,

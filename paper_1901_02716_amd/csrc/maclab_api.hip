@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -42,6 +43,7 @@ struct maclab_s {
   bool plan_set = false;       // chosen by maclab_set_tiling / maclab_autotune
   int adj_kernel = -1;         // reverse step: -1 automatic, 0 general, 3 fast D2Q9
   Fast2DShape adj2;            // its tiling when set explicitly
+  bool view = false;           // one lattice of a batch: memory owned by the batch
   std::string err;
 };
 
@@ -575,6 +577,7 @@ size_t maclab_adjoint_bytes(maclab_t h) {
 
 int maclab_adjoint_seed(maclab_t h, const void* state_T, const double* dLdu, void* adj) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (h->view) return fail(h, MACLAB_EUNSUPPORTED, "reverse mode is not available on a lattice of a batch");
   if (!state_T || !dLdu || !adj) return fail(h, MACLAB_EINVAL, "state_T, dLdu and adj must be device pointers");
   int rc = check_faces(h);
   if (rc) return rc;
@@ -585,6 +588,7 @@ int maclab_adjoint_seed(maclab_t h, const void* state_T, const double* dLdu, voi
 
 int maclab_adjoint_reset(maclab_t h) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (h->view) return fail(h, MACLAB_EUNSUPPORTED, "reverse mode is not available on a lattice of a batch");
   HIP_TRY(h, launch_zero_doubles(h->gslots, (int64_t)(h->L.adjoint_bytes / sizeof(double)), h->stream));
   return MACLAB_OK;
 }
@@ -645,6 +649,7 @@ int maclab_get_adjoint_tiling(maclab_t h, int out[3]) {
 
 int maclab_adjoint_step(maclab_t h, const void* state_n, const void* adj_np1, void* adj_n) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (h->view) return fail(h, MACLAB_EUNSUPPORTED, "reverse mode is not available on a lattice of a batch");
   if (!state_n || !adj_np1 || !adj_n || adj_np1 == adj_n)
     return fail(h, MACLAB_EINVAL, "state and adjoint buffers must be device pointers, adj_np1 != adj_n");
   int rc = check_faces(h);
@@ -656,6 +661,7 @@ int maclab_adjoint_step(maclab_t h, const void* state_n, const void* adj_np1, vo
 int maclab_adjoint_segment(maclab_t h, const void* ckpt, void* states, int64_t nsteps, int64_t step_index,
                            void* adj_a, void* adj_b, int* which) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (h->view) return fail(h, MACLAB_EUNSUPPORTED, "reverse mode is not available on a lattice of a batch");
   if (!ckpt || !adj_a || !adj_b || !which || adj_a == adj_b || (*which != 0 && *which != 1))
     return fail(h, MACLAB_EINVAL, "ckpt, adj_a, adj_b (distinct) and which (0 or 1) are required");
   if (nsteps < 1 || step_index < 0) return fail(h, MACLAB_EINVAL, "nsteps must be >= 1 and step_index >= 0");
@@ -686,6 +692,7 @@ int maclab_adjoint_segment(maclab_t h, const void* ckpt, void* states, int64_t n
 int maclab_adjoint_result(maclab_t h, const void* state0, const void* adj0, double* dLdu0, double* dLdrho0,
                           double dLdG[3]) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (h->view) return fail(h, MACLAB_EUNSUPPORTED, "reverse mode is not available on a lattice of a batch");
   if (!adj0) return fail(h, MACLAB_EINVAL, "adj0 is NULL");
   if (dLdu0) {
     if (!state0) return fail(h, MACLAB_EINVAL, "state0 is NULL");
@@ -704,8 +711,496 @@ int maclab_adjoint_result(maclab_t h, const void* state0, const void* adj0, doub
   return MACLAB_OK;
 }
 
-void maclab_destroy(maclab_t h) { delete h; }
+void maclab_destroy(maclab_t h) {
+  if (h && !h->view) delete h;  // a batch's lattices go with the batch
+}
 
 const char* maclab_last_error(maclab_t h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+}  // extern "C"
+
+// ===================================================================== batch
+// Many D2Q9 lattices in one state allocation, advanced by one launch per step
+// over a table of work items (lattice, x-segment, band of rows); a run of
+// steps is captured once in a HIP graph and replayed.
+
+struct maclab_batch_s {
+  int count = 0;
+  int precision = 0;
+  double rho_ref = 1.0;
+  uint64_t seed = 0;
+  hipStream_t stream = nullptr;  // the caller's
+  hipStream_t priv = nullptr;    // graph capture and replay (default priority)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<maclab_s*> lat;
+  std::vector<int64_t> base;     // element offset of each lattice in a state buffer
+  char* state[2] = {nullptr, nullptr};
+  Lattice2D* table = nullptr;    // device
+  int4* items = nullptr;         // device
+  int64_t max_items = 0;
+  int kx = 1, rows = 16;
+  int nitems = 0;
+  bool uploaded = false;
+  int up_kx = 0, up_rows = 0;
+  std::vector<Lattice2D> table_host;
+  std::vector<int4> items_host;
+  int graph_steps = 32;          // steps per captured graph (even; 0: no graph)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int cus = 256;
+  std::string err;
+};
+
+namespace {
+
+int bfail(maclab_batch_t b, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int bfail(maclab_batch_t b, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (b)
+    b->err = buf;
+  else
+    g_err = buf;
+  return code;
+}
+
+#define BHIP_TRY(b, expr)                                                                             \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess) return bfail((b), MACLAB_EHIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+constexpr int kBatchRowsMin = 4;
+
+struct BatchLayout {
+  std::vector<Layout> L;
+  std::vector<size_t> off;  // byte offset of each lattice in a state buffer
+  size_t states = 0, partial = 0, staging = 0, adjoint = 0, table = 0, items = 0, total = 0;
+  int64_t max_items = 0;
+};
+
+int batch_layout(const maclab_config* cfgs, int count, BatchLayout* B, std::string* why) {
+  if (!cfgs || count < 1) {
+    *why = "need at least one lattice";
+    return MACLAB_EINVAL;
+  }
+  B->L.resize(count);
+  B->off.resize(count);
+  for (int i = 0; i < count; ++i) {
+    const maclab_config& c = cfgs[i];
+    std::string w;
+    const int rc = make_layout(&c, &B->L[i], &w);
+    if (rc != MACLAB_OK) {
+      *why = "lattice " + std::to_string(i) + ": " + w;
+      return rc;
+    }
+    if (c.lattice != MACLAB_D2Q9) {
+      *why = "lattice " + std::to_string(i) + ": a batch holds D2Q9 lattices only";
+      return MACLAB_EUNSUPPORTED;
+    }
+    if (c.precision != cfgs[0].precision || c.rho_ref != cfgs[0].rho_ref || c.seed != cfgs[0].seed ||
+        c.stream != cfgs[0].stream) {
+      *why = "lattice " + std::to_string(i) + ": precision, rho_ref, seed and stream must match lattice 0";
+      return MACLAB_EINVAL;
+    }
+    if (c.n[0] >= (int64_t(1) << 20) || c.n[1] >= (int64_t(1) << 20)) {
+      *why = "lattice " + std::to_string(i) + ": extents must be below 2^20";
+      return MACLAB_EINVAL;
+    }
+    B->off[i] = B->states;
+    B->states += round_up(B->L[i].state_bytes, kAlign);
+    B->partial = std::max(B->partial, B->L[i].partial_bytes);
+    B->staging = std::max(B->staging, B->L[i].staging_bytes);
+    B->adjoint = std::max(B->adjoint, B->L[i].adjoint_bytes);
+    B->max_items += ((B->L[i].nx + 63) / 64) * ((B->L[i].ny + kBatchRowsMin - 1) / kBatchRowsMin);
+  }
+  if (B->max_items > (int64_t(1) << 30)) {
+    *why = "too many work items";
+    return MACLAB_EINVAL;
+  }
+  B->table = round_up(sizeof(Lattice2D) * (size_t)count, kAlign);
+  B->items = round_up(sizeof(int4) * (size_t)B->max_items, kAlign);
+  B->total = 2 * B->states + B->partial + B->staging + B->adjoint + B->table + B->items;
+  return MACLAB_OK;
+}
+
+// Lattice table and work items of a tiling, from the lattices' current
+// faces and body forces.
+int batch_plan(maclab_batch_t b, int kx, int rows, std::vector<Lattice2D>* table, std::vector<int4>* items) {
+  if (kx != 1 && kx != 2) return bfail(b, MACLAB_EINVAL, "kx must be 1 or 2");
+  if (rows < kBatchRowsMin) return bfail(b, MACLAB_EINVAL, "rows per work item must be >= %d", kBatchRowsMin);
+  table->assign(b->count, Lattice2D{});
+  items->clear();
+  for (int i = 0; i < b->count; ++i) {
+    maclab_s* h = b->lat[i];
+    const int rc = check_faces(h);
+    if (rc) return bfail(b, rc, "lattice %d: %s", i, h->err.c_str());
+    const StepParams p = make_params(h);
+    if (!fast2d_supported(h->L, p))
+      return bfail(b, MACLAB_EUNSUPPORTED, "lattice %d: a periodic x extent must be a multiple of 64", i);
+    if (!p.fixed[0] && h->L.nx % (64 * kx) != 0)
+      return bfail(b, MACLAB_EINVAL, "lattice %d: periodic x extent %lld is not a multiple of %d", i,
+                   (long long)h->L.nx, 64 * kx);
+    Lattice2D& t = (*table)[i];
+    t.nx = (int)h->L.nx;
+    t.ny = (int)h->L.ny;
+    t.pitch = t.nx;
+    t.xper = !p.fixed[0];
+    t.yper = !p.fixed[1];
+    t.aligned = (t.nx % kx) == 0;
+    t.gx = p.g[0];
+    t.gy = p.g[1];
+    t.base = b->base[i];
+    t.plane = h->L.plane;
+    const int nseg = (t.nx + 64 * kx - 1) / (64 * kx);
+    const int ylo = p.fixed[1] ? 1 : 0, nyo = p.fixed[1] ? t.ny - 2 : t.ny;
+    const int nb = (nyo + rows - 1) / rows;
+    for (int band = 0; band < nb; ++band) {
+      const int y0 = ylo + (int)((int64_t)band * nyo / nb), y1 = ylo + (int)((int64_t)(band + 1) * nyo / nb);
+      for (int sg = 0; sg < nseg; ++sg) items->push_back(make_int4(i, sg * 64 * kx, y0, y1));
+    }
+  }
+  if ((int64_t)items->size() > b->max_items) return bfail(b, MACLAB_EINVAL, "too many work items for the workspace");
+  // largest items first, so the tail of the launch is made of small ones
+  std::stable_sort(items->begin(), items->end(), [&](const int4& a, const int4& c) {
+    const int64_t wa = std::min(64 * kx, (*table)[a.x].nx - a.y), wc = std::min(64 * kx, (*table)[c.x].nx - c.y);
+    return (int64_t)(a.w - a.z) * wa > (int64_t)(c.w - c.z) * wc;
+  });
+  return MACLAB_OK;
+}
+
+void drop_graph(maclab_batch_t b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+bool same_lattice(const Lattice2D& a, const Lattice2D& c) {
+  return a.nx == c.nx && a.ny == c.ny && a.pitch == c.pitch && a.xper == c.xper && a.yper == c.yper &&
+         a.aligned == c.aligned && a.gx == c.gx && a.gy == c.gy && a.base == c.base && a.plane == c.plane;
+}
+
+// Makes the device tables match the current tiling, faces and forces.
+int batch_sync(maclab_batch_t b) {
+  std::vector<Lattice2D> table;
+  std::vector<int4> items;
+  int rc = batch_plan(b, b->kx, b->rows, &table, &items);
+  if (rc) return rc;
+  bool same = b->uploaded && b->up_kx == b->kx && b->up_rows == b->rows && table.size() == b->table_host.size();
+  for (size_t i = 0; same && i < table.size(); ++i) same = same_lattice(table[i], b->table_host[i]);
+  if (same) return MACLAB_OK;
+  drop_graph(b);
+  b->table_host.swap(table);
+  b->items_host.swap(items);
+  BHIP_TRY(b, hipMemcpyAsync(b->table, b->table_host.data(), sizeof(Lattice2D) * b->table_host.size(),
+                             hipMemcpyHostToDevice, b->stream));
+  if (!b->items_host.empty())
+    BHIP_TRY(b, hipMemcpyAsync(b->items, b->items_host.data(), sizeof(int4) * b->items_host.size(),
+                               hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));  // the host copies may change before the next sync
+  b->nitems = (int)b->items_host.size();
+  b->uploaded = true;
+  b->up_kx = b->kx;
+  b->up_rows = b->rows;
+  return MACLAB_OK;
+}
+
+int batch_consistent(maclab_batch_t b) {
+  for (int i = 1; i < b->count; ++i)
+    if (b->lat[i]->cur != b->lat[0]->cur || b->lat[i]->steps != b->lat[0]->steps)
+      return bfail(b, MACLAB_EINVAL, "lattice %d was stepped on its own; the batch steps all lattices together", i);
+  return MACLAB_OK;
+}
+
+void batch_advance(maclab_batch_t b, int64_t n) {
+  for (maclab_s* h : b->lat) {
+    h->cur ^= (int)(n & 1);
+    h->steps += n;
+  }
+}
+
+int batch_launch(maclab_batch_t b, hipStream_t s, int cur, int64_t step) {
+  const uint32_t key = sr_key(b->seed, (uint64_t)step);
+  BHIP_TRY(b, launch_step_fast2d_items(b->precision, b->kx, b->state[cur], b->state[cur ^ 1], b->table, b->items,
+                                       b->nitems, b->rho_ref, key, s));
+  return MACLAB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t maclab_batch_workspace_bytes(const maclab_config* cfgs, int count) {
+  BatchLayout B;
+  std::string why;
+  if (batch_layout(cfgs, count, &B, &why) != MACLAB_OK) return 0;
+  return B.total;
+}
+
+int maclab_batch_init(const maclab_config* cfgs, int count, void* workspace, size_t workspace_bytes,
+                      maclab_batch_t* out) {
+  if (!out) return bfail(nullptr, MACLAB_EINVAL, "out is NULL");
+  *out = nullptr;
+  BatchLayout B;
+  std::string why;
+  int rc = batch_layout(cfgs, count, &B, &why);
+  if (rc) return bfail(nullptr, rc, "maclab_batch_init: %s", why.c_str());
+  if (!workspace || (uintptr_t)workspace % kAlign)
+    return bfail(nullptr, MACLAB_EWORKSPACE, "maclab_batch_init: workspace must be %zu-byte aligned device memory",
+                 kAlign);
+  if (workspace_bytes < B.total)
+    return bfail(nullptr, MACLAB_EWORKSPACE, "maclab_batch_init: workspace has %zu bytes, needs %zu",
+                 workspace_bytes, B.total);
+  maclab_batch_t b = new (std::nothrow) maclab_batch_s();
+  if (!b) return bfail(nullptr, MACLAB_EINVAL, "maclab_batch_init: out of host memory");
+  b->count = count;
+  b->precision = cfgs[0].precision;
+  b->rho_ref = cfgs[0].rho_ref;
+  b->seed = cfgs[0].seed;
+  b->stream = (hipStream_t)cfgs[0].stream;
+  b->max_items = B.max_items;
+  char* ws = (char*)workspace;
+  b->state[0] = ws;
+  b->state[1] = ws + B.states;
+  char* shared = ws + 2 * B.states;
+  double* partials = (double*)shared;
+  char* staging = shared + B.partial;
+  double* gslots = (double*)(staging + B.staging);
+  b->table = (Lattice2D*)(shared + B.partial + B.staging + B.adjoint);
+  b->items = (int4*)((char*)b->table + B.table);
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+    b->cus = cus;
+  b->lat.reserve(count);
+  b->base.resize(count);
+  const int bytes = B.L[0].bytes;
+  for (int i = 0; i < count; ++i) {
+    maclab_s* h = new (std::nothrow) maclab_s();
+    if (!h) {
+      maclab_batch_destroy(b);
+      return bfail(nullptr, MACLAB_EINVAL, "maclab_batch_init: out of host memory");
+    }
+    h->view = true;
+    h->cfg = cfgs[i];
+    h->cfg.workspace = nullptr;
+    h->cfg.workspace_bytes = 0;
+    h->L = B.L[i];
+    h->stream = b->stream;
+    h->state[0] = b->state[0] + B.off[i];
+    h->state[1] = b->state[1] + B.off[i];
+    h->partials = partials;
+    h->result = partials + (size_t)kDiagBlocks * kDiagValues;
+    h->staging = staging;
+    h->L.staging_bytes = B.staging;
+    h->gslots = gslots;
+    for (int f = 0; f < 6; ++f) {
+      h->fv.kind[f] = MACLAB_BC_PERIODIC;
+      h->fv.rho[f] = cfgs[i].rho_ref;
+      for (int c = 0; c < 3; ++c) h->fv.u[f][c] = 0.0;
+    }
+    h->cus = b->cus;
+    h->e = 6.0 * cfgs[i].nu / cfgs[i].dx;  // Eq. (6)
+    h->dt = cfgs[i].dx / h->e;
+    b->lat.push_back(h);
+    b->base[i] = (int64_t)(B.off[i] / (size_t)bytes);
+  }
+  hipError_t e1 = hipMemsetAsync(ws, 0, 2 * B.states, b->stream);
+  if (e1 == hipSuccess) e1 = hipStreamCreateWithFlags(&b->priv, hipStreamNonBlocking);
+  if (e1 == hipSuccess) e1 = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+  if (e1 == hipSuccess) e1 = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  if (e1 != hipSuccess) {
+    rc = bfail(nullptr, MACLAB_EHIP, "maclab_batch_init: %s", hipGetErrorString(e1));
+    maclab_batch_destroy(b);
+    return rc;
+  }
+  b->kx = 2;
+  for (int i = 0; i < count; ++i)
+    if (B.L[i].nx < 128) b->kx = 1;
+  *out = b;
+  return MACLAB_OK;
+}
+
+maclab_t maclab_batch_lattice(maclab_batch_t b, int index) {
+  if (!b || index < 0 || index >= b->count) return nullptr;
+  return b->lat[index];
+}
+
+int maclab_batch_count(maclab_batch_t b) { return b ? b->count : 0; }
+
+int maclab_batch_step(maclab_batch_t b, int64_t n) {
+  if (!b) return bfail(nullptr, MACLAB_EINVAL, "batch is NULL");
+  if (n < 0) return bfail(b, MACLAB_EINVAL, "negative step count");
+  int rc = batch_consistent(b);
+  if (!rc) rc = batch_sync(b);
+  if (rc) return rc;
+  int64_t done = 0;
+  const bool graphs = b->graph_steps > 0 && b->precision != MACLAB_S16;  // S16 keys every step's rounding
+  if (graphs && n >= b->graph_steps + (b->lat[0]->cur & 1)) {
+    if (b->lat[0]->cur & 1) {  // the graph starts from buffer 0
+      rc = batch_launch(b, b->stream, 1, b->lat[0]->steps);
+      if (rc) return rc;
+      batch_advance(b, 1);
+      done = 1;
+    }
+    if (!b->exec) {
+      BHIP_TRY(b, hipStreamBeginCapture(b->priv, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < b->graph_steps; ++k) {
+        rc = batch_launch(b, b->priv, k & 1, 0);
+        if (rc) {
+          hipGraph_t g = nullptr;
+          (void)hipStreamEndCapture(b->priv, &g);
+          if (g) (void)hipGraphDestroy(g);
+          return rc;
+        }
+      }
+      BHIP_TRY(b, hipStreamEndCapture(b->priv, &b->graph));
+      BHIP_TRY(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    const int64_t reps = (n - done) / b->graph_steps;
+    BHIP_TRY(b, hipEventRecord(b->ev_in, b->stream));
+    BHIP_TRY(b, hipStreamWaitEvent(b->priv, b->ev_in, 0));
+    for (int64_t r = 0; r < reps; ++r) BHIP_TRY(b, hipGraphLaunch(b->exec, b->priv));
+    BHIP_TRY(b, hipEventRecord(b->ev_out, b->priv));
+    BHIP_TRY(b, hipStreamWaitEvent(b->stream, b->ev_out, 0));
+    batch_advance(b, reps * b->graph_steps);
+    done += reps * b->graph_steps;
+  }
+  for (; done < n; ++done) {
+    rc = batch_launch(b, b->stream, b->lat[0]->cur, b->lat[0]->steps);
+    if (rc) return rc;
+    batch_advance(b, 1);
+  }
+  return MACLAB_OK;
+}
+
+int maclab_batch_step_separate(maclab_batch_t b, int64_t n) {
+  if (!b) return bfail(nullptr, MACLAB_EINVAL, "batch is NULL");
+  if (n < 0) return bfail(b, MACLAB_EINVAL, "negative step count");
+  int rc = batch_consistent(b);
+  if (rc) return rc;
+  std::vector<Fast2DShape> shapes(b->count);
+  for (int i = 0; i < b->count; ++i) {
+    maclab_s* h = b->lat[i];
+    rc = check_faces(h);
+    if (rc) return bfail(b, rc, "lattice %d: %s", i, h->err.c_str());
+    const StepParams p = make_params(h);
+    if (!fast2d_supported(h->L, p)) return bfail(b, MACLAB_EUNSUPPORTED, "lattice %d: not a fast D2Q9 lattice", i);
+    shapes[i] = fast2d_default_shape(h->L, p, b->cus);
+  }
+  for (int64_t k = 0; k < n; ++k) {
+    for (int i = 0; i < b->count; ++i) {
+      maclab_s* h = b->lat[i];
+      StepParams p = make_params(h);
+      BHIP_TRY(b, launch_step_fast2d(h->L, h->state[h->cur], h->state[h->cur ^ 1], p, shapes[i], b->stream));
+    }
+    batch_advance(b, 1);
+  }
+  return MACLAB_OK;
+}
+
+int maclab_batch_get_tiling(maclab_batch_t b, int out[3]) {
+  if (!b) return bfail(nullptr, MACLAB_EINVAL, "batch is NULL");
+  if (!out) return bfail(b, MACLAB_EINVAL, "out is NULL");
+  const int rc = batch_sync(b);
+  if (rc) return rc;
+  out[0] = b->kx;
+  out[1] = b->rows;
+  out[2] = b->nitems;
+  return MACLAB_OK;
+}
+
+int maclab_batch_set_tiling(maclab_batch_t b, int kx, int rows) {
+  if (!b) return bfail(nullptr, MACLAB_EINVAL, "batch is NULL");
+  std::vector<Lattice2D> t;
+  std::vector<int4> it;
+  int rc = batch_plan(b, kx, rows, &t, &it);  // validates
+  if (rc) return rc;
+  b->kx = kx;
+  b->rows = rows;
+  return batch_sync(b);
+}
+
+int maclab_batch_set_graph(maclab_batch_t b, int steps_per_graph) {
+  if (!b) return bfail(nullptr, MACLAB_EINVAL, "batch is NULL");
+  if (steps_per_graph < 0 || steps_per_graph % 2 || steps_per_graph > 4096)
+    return bfail(b, MACLAB_EINVAL, "steps per graph must be 0 or an even number up to 4096");
+  if (steps_per_graph != b->graph_steps) drop_graph(b);
+  b->graph_steps = steps_per_graph;
+  return MACLAB_OK;
+}
+
+int maclab_batch_autotune(maclab_batch_t b, int reps, double* best_ms) {
+  if (!b) return bfail(nullptr, MACLAB_EINVAL, "batch is NULL");
+  if (reps < 1) return bfail(b, MACLAB_EINVAL, "reps must be >= 1");
+  int rc = batch_consistent(b);
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  BHIP_TRY(b, hipEventCreate(&e0));
+  hipError_t ee = hipEventCreate(&e1);
+  if (ee != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return bfail(b, MACLAB_EHIP, "hipEventCreate: %s", hipGetErrorString(ee));
+  }
+  const int kx0 = b->kx, rows0 = b->rows;
+  double best = 1e300;
+  int bkx = kx0, brows = rows0;
+  const int cur = b->lat[0]->cur;
+  for (int kx : {1, 2}) {
+    for (int rows : {4, 8, 16, 32, 64, 128}) {
+      std::vector<Lattice2D> t;
+      std::vector<int4> it;
+      if (batch_plan(b, kx, rows, &t, &it) != MACLAB_OK) continue;
+      b->kx = kx;
+      b->rows = rows;
+      rc = batch_sync(b);
+      // the spare buffer takes the output: the state is not advanced
+      if (!rc) rc = batch_launch(b, b->stream, cur, b->lat[0]->steps);
+      hipError_t he = hipSuccess;
+      if (!rc) he = hipEventRecord(e0, b->stream);
+      for (int r = 0; !rc && he == hipSuccess && r < reps; ++r) rc = batch_launch(b, b->stream, cur, b->lat[0]->steps);
+      if (!rc && he == hipSuccess) he = hipEventRecord(e1, b->stream);
+      if (!rc && he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0;
+      if (!rc && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (rc || he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc) return rc;
+        return bfail(b, MACLAB_EHIP, "autotune timing: %s", hipGetErrorString(he));
+      }
+      const double per = ms / reps;
+      if (per < best) {
+        best = per;
+        bkx = kx;
+        brows = rows;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->kx = bkx;
+  b->rows = brows;
+  rc = batch_sync(b);
+  if (rc) return rc;
+  if (best_ms) *best_ms = best;
+  return MACLAB_OK;
+}
+
+void maclab_batch_destroy(maclab_batch_t b) {
+  if (!b) return;
+  drop_graph(b);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->priv) (void)hipStreamDestroy(b->priv);
+  for (maclab_s* h : b->lat) delete h;
+  delete b;
+}
+
+const char* maclab_batch_last_error(maclab_batch_t b) { return b ? b->err.c_str() : g_err.c_str(); }
 
 }  // extern "C"

@@ -233,7 +233,27 @@ class Simulation:
         assert src.numel() * src.element_size() >= self.state_bytes()
         _lib.check(self.lib.maclab_load_state(self.h, src.data_ptr()), self.h)
 
+    @classmethod
+    def _view(cls, lib, h, lattice: int, n, precision: str, device, stream, owner) -> "Simulation":
+        """A Simulation over a handle the library owns (one lattice of a
+        batch); `owner` is kept alive with it."""
+        self = cls.__new__(cls)
+        self.lib = lib
+        self.h = ctypes.c_void_p(h)
+        self.device = torch.device(device)
+        self.q = int(lattice)
+        self.d = 2 if self.q == 9 else 3
+        self.n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
+        self.N = self.n[0] * self.n[1] * self.n[2]
+        self.precision = precision
+        self.stream = stream
+        self._owner = owner
+        return self
+
     def close(self) -> None:
+        if getattr(self, "_owner", None) is not None:
+            self.h = ctypes.c_void_p()  # the batch owns the handle
+            return
         if getattr(self, "h", None) is not None and self.h.value:
             self.lib.maclab_destroy(self.h)
             self.h = ctypes.c_void_p()

@@ -1,0 +1,133 @@
+"""GPU batch of D2Q9 cavities (maclab_batch_*): one launch per step over all
+lattices, captured in HIP graphs.
+
+The batch must reproduce, bit for bit, each lattice stepped on its own with
+the fast D2Q9 kernel (the same arithmetic on the same nodes), for every
+tiling, with or without graphs and with the one-launch-per-lattice schedule;
+and the FP32 results of stable cavities must match the FP64 oracle to 1e-5
+relative L2.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1901_02716_amd import MaclabError, Simulation, cavities, workloads
+from conftest import rel_l2, to_problem
+
+pytestmark = pytest.mark.gpu
+
+# sizes with odd and even extents, below and above one 64-node segment
+DRAWS = [(21, 40.0, 0.1), (64, 100.0, 0.07), (65, 90.0, 0.1), (100, 150.0, 0.05), (129, 200.0, 0.1),
+         (37, 60.0, 0.08), (200, 300.0, 0.1), (257, 400.0, 0.1), (130, 180.0, 0.06), (3, 10.0, 0.1)]
+
+
+def _single(N, Re, U, precision):
+    case = workloads.cavity_2d(n=N, Re=Re, U=U)
+    sim = Simulation(9, case.n, case.dx, case.nu, precision=precision)
+    for face, (rb, ub) in case.fixed.items():
+        sim.set_bc(face, rb, ub)
+    return sim
+
+
+def _state(sim):
+    return sim.save_state().cpu()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "hilo", "s16"])
+def test_batch_equals_single_lattices(precision):
+    steps = 70  # two graph replays of 32 steps plus direct steps
+    print(f"[batch] {len(DRAWS)} cavities {precision} steps={steps}", flush=True)
+    b = cavities(DRAWS, precision=precision)
+    b.step(steps)
+    for i, (N, Re, U) in enumerate(DRAWS):
+        sim = _single(N, Re, U, precision)
+        sim.step(steps)
+        assert torch.equal(_state(b[i]), _state(sim)), f"lattice {i} (N={N}) differs"
+    assert b[0].params()["steps"] == steps
+
+
+def test_batch_graph_tiling_and_schedule_are_bitwise_identical():
+    ref = cavities(DRAWS, precision="fp32")
+    ref.set_graph(0)
+    ref.step(41)
+    want = [_state(ref[i]) for i in range(len(DRAWS))]
+    for kx, rows, graph in [(1, 4, 32), (2, 16, 8), (1, 128, 2), (2, 7, 0)]:
+        b = cavities(DRAWS, precision="fp32")
+        b.set_tiling(kx, rows)
+        b.set_graph(graph)
+        b.step(41)
+        for i in range(len(DRAWS)):
+            assert torch.equal(_state(b[i]), want[i]), (kx, rows, graph, i)
+    b = cavities(DRAWS, precision="fp32")
+    b.step_separate(41)
+    for i in range(len(DRAWS)):
+        assert torch.equal(_state(b[i]), want[i])
+
+
+def test_batch_autotune_does_not_advance():
+    b = cavities(DRAWS, precision="fp32")
+    b.step(5)
+    before = [_state(b[i]) for i in range(len(DRAWS))]
+    ms = b.autotune(reps=3)
+    assert ms > 0
+    t = b.tiling()
+    assert t["kx"] in (1, 2) and t["rows"] >= 4 and t["items"] > 0
+    for i in range(len(DRAWS)):
+        assert torch.equal(_state(b[i]), before[i])
+    assert b[0].params()["steps"] == 5
+
+
+def test_batch_matches_oracle_fp32():
+    draws = [(33, 40.0, 0.1), (48, 70.0, 0.1), (70, 100.0, 0.08)]
+    steps = 300
+    b = cavities(draws, precision="fp32")
+    b.step(steps)
+    for i, (N, Re, U) in enumerate(draws):
+        case = workloads.cavity_2d(n=N, Re=Re, U=U)
+        orho, ou = oracle.run(to_problem(case), case.rho, case.u, steps)
+        rho, u = b[i].fields()
+        print(f"  N={N} relL2 u={rel_l2(u, ou):.2e} rho={rel_l2(rho, orho):.2e}", flush=True)
+        assert rel_l2(u, ou) < 1e-5
+        assert rel_l2(rho, orho) < 1e-5
+
+
+def test_batch_rejects_inconsistent_steps_and_bad_tiling():
+    b = cavities(DRAWS[:3], precision="fp32")
+    b[1].step(1)
+    with pytest.raises(MaclabError):
+        b.step(1)
+    b2 = cavities(DRAWS[:3], precision="fp32")
+    with pytest.raises(MaclabError):
+        b2.set_tiling(3, 16)
+    with pytest.raises(MaclabError):
+        b2.set_tiling(1, 2)
+    with pytest.raises(MaclabError):
+        b2.set_graph(3)
+    with pytest.raises(MaclabError):
+        b2[0].adjoint_reset()
+
+
+@pytest.mark.slow
+def test_full_batch_512_cavities_sampled_against_oracle():
+    """The 512-cavity draw (seed 4): every cavity advanced together; the
+    stable cavities (lattice Reynolds number U dx / nu <= 2.5) among the
+    smallest are checked against the oracle, and the count of cavities that
+    went non-finite is reported."""
+    draws = workloads.batch_draw()
+    steps = 100
+    print(f"[batch] 512 cavities, {sum(N * N for N, _, _ in draws)} nodes, steps={steps}", flush=True)
+    b = cavities(draws, precision="fp32")
+    b.autotune(reps=2)
+    b.step(steps)
+    rle = [Re / (N - 1) for N, Re, U in draws]
+    stable = sorted((N, i) for i, (N, Re, U) in enumerate(draws) if rle[i] <= 2.5)[:4]
+    for N, i in stable:
+        _, Re, U = draws[i]
+        case = workloads.cavity_2d(n=N, Re=Re, U=U)
+        orho, ou = oracle.run(to_problem(case), case.rho, case.u, steps)
+        rho, u = b[i].fields()
+        assert rel_l2(u, ou) < 1e-5 and rel_l2(rho, orho) < 1e-5, (i, N)
+    nonfinite = sum(1 for i in range(len(draws)) if b[i].diagnostics()[6] > 0)
+    print(f"  non-finite cavities after {steps} steps: {nonfinite} of 512", flush=True)
+    assert np.isfinite(b[stable[0][1]].diagnostics()[0])
