@@ -163,4 +163,61 @@ __device__ __forceinline__ double dpp_from_right(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// ------------------------------------------------------- buffer addressing
+// Raw buffer loads and stores through a buffer resource of one field plane.
+// A byte offset of kOutOfRange lies past every resource (resources are kept
+// below 2^31 bytes): such a load returns zero and such a store is dropped by
+// the hardware's range check, so lanes without a node still execute the same
+// memory instructions as the others and every wavefront issues the same
+// sequence of memory operations whatever its position.
+constexpr int kOutOfRange = (int)0x80000000;
+using buf_t = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ buf_t make_buf(const void* base, int64_t bytes) {
+  // stride 0 (raw), range `bytes`, gfx9 data format word
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int BYTES>
+struct BufIO;
+template <>
+struct BufIO<2> {
+  using U = unsigned short;
+  __device__ static U load(buf_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0); }
+  template <int AUX>
+  __device__ static void store(U v, buf_t r, int off) { __builtin_amdgcn_raw_buffer_store_b16(v, r, off, 0, AUX); }
+};
+template <>
+struct BufIO<4> {
+  using U = unsigned int;
+  __device__ static U load(buf_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0); }
+  template <int AUX>
+  __device__ static void store(U v, buf_t r, int off) { __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, AUX); }
+};
+template <>
+struct BufIO<8> {
+  typedef unsigned int U __attribute__((ext_vector_type(2)));
+  __device__ static U load(buf_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0); }
+  template <int AUX>
+  __device__ static void store(U v, buf_t r, int off) { __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, AUX); }
+};
+template <>
+struct BufIO<16> {
+  typedef unsigned int U __attribute__((ext_vector_type(4)));
+  __device__ static U load(buf_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0); }
+  template <int AUX>
+  __device__ static void store(U v, buf_t r, int off) { __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, AUX); }
+};
+
+// Loads / stores a trivially copyable V (2, 4, 8 or 16 bytes) at a byte offset;
+// AUX is the cache-policy word (2: non-temporal).
+template <class V>
+__device__ __forceinline__ V buf_load(buf_t r, int off) {
+  return __builtin_bit_cast(V, BufIO<sizeof(V)>::load(r, off));
+}
+template <class V, int AUX = 0>
+__device__ __forceinline__ void buf_store(const V& v, buf_t r, int off) {
+  BufIO<sizeof(V)>::template store<AUX>(__builtin_bit_cast(typename BufIO<sizeof(V)>::U, v), r, off);
+}
+
 }  // namespace maclab

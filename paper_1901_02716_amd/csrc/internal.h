@@ -89,8 +89,9 @@ struct Lattice2D {
   int64_t plane;      // elements between field planes
 };
 // A batch step: work item {lattice, x0, y0, y1} of a device table, one
-// wavefront each, all lattices in one launch.
-hipError_t launch_step_fast2d_items(int precision, int kx, const void* src, void* dst, const Lattice2D* lat,
+// wavefront each, all lattices in one launch. vec: every lattice of the items
+// has rows that start on a kx-element boundary (x extent a multiple of kx).
+hipError_t launch_step_fast2d_items(int precision, int kx, bool vec, const void* src, void* dst, const Lattice2D* lat,
                                     const int4* items, int nitems, double rho_ref, uint32_t sr_key, hipStream_t s);
 
 // Reverse mode (kernels_adjoint.hip). Adjoint buffers hold (Rbar, Mbar) in

@@ -18,6 +18,8 @@
 //    depend on the segmentation or banding.
 #include "internal.h"
 
+#include <type_traits>
+
 namespace maclab {
 
 struct Fast2DParams {
@@ -77,16 +79,24 @@ struct RowAcc2 {
 // from spending registers on hoisting).
 template <class C, int KX>
 struct Occupancy2D {
-  static constexpr int value = (sizeof(typename C::T) == 8 && KX > 1) ? 2 : 4;
+  static constexpr int value = sizeof(typename C::T) == 8 ? (KX > 1 ? 2 : 3) : 4;
 };
 
-template <class C, int KX>
+// Memory access of one wavefront goes through buffer resources of the three
+// field planes of its lattice, and every wavefront issues the same sequence of
+// loads and stores in every row step: lanes without a node (past the end of
+// the row, the halo of an interior lane, a row past the band) use an
+// out-of-range offset. The compiler's wait for a row's loads then only has to
+// let the previous row's stores stay in flight. VEC: rows start on a KX-element
+// boundary, so a lane moves its KX nodes with one vector access per field.
+template <class C, int KX, bool VEC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy2D<C, KX>::value)))
-void step_d2q9_fast(const typename C::elem* __restrict__ src,
-                                                      typename C::elem* __restrict__ dst, Fast2DParams p) {
+void step_d2q9_fast(const typename C::elem* __restrict__ src, typename C::elem* __restrict__ dst, Fast2DParams p) {
   using T = typename C::T;
   using E = typename C::elem;
+  using V = RowVec2<E, KX>;
   constexpr int SW = 64 * KX;
+  constexpr int EB = (int)sizeof(E);
   const int lane = threadIdx.x & 63;
   // the work item is uniform across the wavefront: keep it in scalar registers
   const int g = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
@@ -106,8 +116,13 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src,
     y0 = p.ylo + (int)((int64_t)band * p.nyo / p.nband);
     y1 = p.ylo + (int)((int64_t)(band + 1) * p.nyo / p.nband);
   }
-  const E* s = src + lt.base;
-  E* d = dst + lt.base;
+  const int64_t pbytes = lt.plane * EB;
+  buf_t rs[3], rd[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    rs[f] = make_buf(src + lt.base + f * lt.plane, pbytes);
+    rd[f] = make_buf(dst + lt.base + f * lt.plane, pbytes);
+  }
   const T rho_ref = (T)p.rho_ref;
   const int xb = x0 + KX * lane;
   // the segment spans the row (one wavefront): neighbours wrap through DPP;
@@ -116,52 +131,63 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src,
   const bool full_row = x0 == 0 && lt.nx == SW;
   const bool need_left = !full_row && (x0 > 0 || lt.xper);
   const bool need_right = !full_row && (x0 + SW < lt.nx || lt.xper);
+  int hx = lane == 0 ? x0 - 1 : x0 + SW;
+  hx = hx < 0 ? hx + lt.nx : (hx >= lt.nx ? hx - lt.nx : hx);
+  const bool halo_lane = (lane == 0 && need_left) || (lane == 63 && need_right);
   auto ywrap = [&](int y) { return lt.yper ? (y + lt.ny) % lt.ny : y; };
 
-  T dr[KX], ux[KX], uy[KX];
-  T hdr = 0, hux = 0, huy = 0;  // halo node of lanes 0 / 63
-  const bool vec = lt.aligned && xb + KX <= lt.nx;
-  auto load_row = [&](int y) {
-    const int64_t rb = (int64_t)lt.pitch * ywrap(y);
-    if (vec) {
-      const RowVec2<E, KX> a = *reinterpret_cast<const RowVec2<E, KX>*>(s + rb + xb);
-      const RowVec2<E, KX> b = *reinterpret_cast<const RowVec2<E, KX>*>(s + lt.plane + rb + xb);
-      const RowVec2<E, KX> c = *reinterpret_cast<const RowVec2<E, KX>*>(s + 2 * lt.plane + rb + xb);
+  // raw rows: a ring of three rows in flight (row y in slot (y - y0 + 1) mod
+  // 3), the source row being pushed (cur) and the row before it (prev, whose
+  // wall nodes are stored back unchanged)
+  V ring[3][3], cur[3], prev[3];
+  E hring[3][3];
+  auto load_row = [&](int y, bool valid, V (&ld)[3], E (&hld)[3]) {
+    const int rb = (int)((int64_t)lt.pitch * ywrap(y) * EB);
+    if constexpr (VEC) {
+      const int off = valid && xb < lt.nx ? rb + xb * EB : kOutOfRange;
 #pragma unroll
-      for (int e = 0; e < KX; ++e) {
-        dr[e] = C::dec(a.v[e], 0);
-        ux[e] = C::dec(b.v[e], 1);
-        uy[e] = C::dec(c.v[e], 2);
-      }
+      for (int f = 0; f < 3; ++f) ld[f] = buf_load<V>(rs[f], off);
     } else {
 #pragma unroll
       for (int e = 0; e < KX; ++e) {
-        int x = xb + e;
-        x = x < lt.nx ? x : lt.nx - 1;  // lanes past a ragged end read a valid node
-        dr[e] = C::dec(s[rb + x], 0);
-        ux[e] = C::dec(s[lt.plane + rb + x], 1);
-        uy[e] = C::dec(s[2 * lt.plane + rb + x], 2);
+        const int off = valid && xb + e < lt.nx ? rb + (xb + e) * EB : kOutOfRange;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) ld[f].v[e] = buf_load<E>(rs[f], off);
       }
     }
-    if ((lane == 0 && need_left) || (lane == 63 && need_right)) {
-      int hx = lane == 0 ? x0 - 1 : x0 + SW;
-      hx = hx < 0 ? hx + lt.nx : (hx >= lt.nx ? hx - lt.nx : hx);
-      hdr = C::dec(s[rb + hx], 0);
-      hux = C::dec(s[lt.plane + rb + hx], 1);
-      huy = C::dec(s[2 * lt.plane + rb + hx], 2);
-    }
+    const int hoff = valid && halo_lane ? rb + hx * EB : kOutOfRange;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) hld[f] = buf_load<E>(rs[f], hoff);
   };
 
   RowAcc2<T, KX> A0, A1, A2;
 #pragma unroll
   for (int e = 0; e < KX; ++e) A0.r[e] = A0.mx[e] = A0.my[e] = A1.r[e] = A1.mx[e] = A1.my[e] = (T)0;
 
-  // Source row ys into rows ys-1 (am), ys (ac), ys+1 (ap, first touched here).
+  // Source row ys into rows ys-1 (am), ys (ac), ys+1 (ap, first touched here);
+  // then destination row ys-1 is complete and stored (STORE), or the same
+  // stores are issued out of range (the first row of the band).
   // Destination node d needs its own links (rest, +-y), the +x-moving links
   // of node d-1 (P) and the -x-moving links of node d+1 (M); it is completed
   // as soon as node d+1 has been evaluated, so few link values stay live.
-  auto source_row = [&](int ys, RowAcc2<T, KX>& am, RowAcc2<T, KX>& ac, RowAcc2<T, KX>& ap) {
+  auto source_row = [&](auto store_c, int ys, RowAcc2<T, KX>& am, RowAcc2<T, KX>& ac, RowAcc2<T, KX>& ap,
+                        V (&ld)[3], E (&hld)[3]) {
 #pragma clang fp contract(off)
+    constexpr bool STORE = decltype(store_c)::value;
+    T dr[KX], ux[KX], uy[KX];
+    E hv[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      prev[f] = cur[f];
+      cur[f] = ld[f];
+      hv[f] = hld[f];
+    }
+#pragma unroll
+    for (int e = 0; e < KX; ++e) {
+      dr[e] = C::dec(cur[0].v[e], 0);
+      ux[e] = C::dec(cur[1].v[e], 1);
+      uy[e] = C::dec(cur[2].v[e], 2);
+    }
     T of0[KX], oyp[KX], oym[KX];   // own links of node e
     T pq[KX], ppp[KX], ppm[KX];    // P links of node e: (1,0)/4, (1,1), (1,-1)
     T mq[KX], mmp[KX], mmm[KX];    // M links of node e: (-1,0)/4, (-1,1), (-1,-1)
@@ -196,8 +222,8 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src,
       if (e >= 2) complete(e - 1, pq[e - 2], ppp[e - 2], ppm[e - 2], mq[e], mmp[e], mmm[e]);
     }
     Links2<T> H;
-    links2<T>(hdr, hux, huy, rho_ref, H);  // meaningful on the edge lanes only
-    if (ys < y1) load_row(ys + 1);
+    links2<T>(C::dec(hv[0], 0), C::dec(hv[1], 1), C::dec(hv[2], 2), rho_ref, H);  // meaningful on halo lanes only
+    load_row(ys + 3, ys + 3 <= y1, ld, hld);  // the slot just consumed takes row ys + 3
     // links entering the lane's first node from the left and last node from the right
     T in_q = dpp_from_left(pq[KX - 1]), in_pp = dpp_from_left(ppp[KX - 1]), in_pm = dpp_from_left(ppm[KX - 1]);
     T in_mq = dpp_from_right(mq[0]), in_mp = dpp_from_right(mmp[0]), in_mm = dpp_from_right(mmm[0]);
@@ -218,58 +244,73 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src,
       complete(KX - 1, pq[KX - 2], ppp[KX - 2], ppm[KX - 2], in_mq, in_mp, in_mm);
     }
     const int yd = ys - 1;
-    if (yd >= y0) {
-      const int64_t rb = (int64_t)lt.pitch * ywrap(yd);
-      RowVec2<E, KX> o0, o1, o2;
+    const int rb = STORE ? (int)((int64_t)lt.pitch * ywrap(yd) * EB) : 0;
+    V o[3];
+#pragma unroll
+    for (int q = 0; q < KX; ++q) {
+      const T drn = am.r[q] * (T)(1.0 / 36.0);
+      T inv;
+      if constexpr (sizeof(T) == 4)
+        inv = __builtin_amdgcn_rcpf(rho_ref + drn);  // v_rcp_f32, 1 ulp
+      else
+        inv = (T)1 / (rho_ref + drn);
+      const T vx = __builtin_fma(am.mx[q], (T)(1.0 / 36.0), (T)lt.gx) * inv;
+      const T vy = __builtin_fma(am.my[q], (T)(1.0 / 36.0), (T)lt.gy) * inv;
+      uint32_t bits = 0;
+      if constexpr (needs_rng<C>::value) bits = sr_node_bits(p.sr_key, (int64_t)lt.pitch * ywrap(yd) + xb + q);
+      o[0].v[q] = C::enc(drn, 0, bits);
+      o[1].v[q] = C::enc(vx, 1, bits);
+      o[2].v[q] = C::enc(vy, 2, bits);
+    }
+    if constexpr (VEC) {
+      // a wall node keeps its stored value (the row before holds it unchanged)
 #pragma unroll
       for (int q = 0; q < KX; ++q) {
-        const T drn = am.r[q] * (T)(1.0 / 36.0);
-        T inv;
-        if constexpr (sizeof(T) == 4)
-          inv = __builtin_amdgcn_rcpf(rho_ref + drn);  // v_rcp_f32, 1 ulp
-        else
-          inv = (T)1 / (rho_ref + drn);
-        const T vx = __builtin_fma(am.mx[q], (T)(1.0 / 36.0), (T)lt.gx) * inv;
-        const T vy = __builtin_fma(am.my[q], (T)(1.0 / 36.0), (T)lt.gy) * inv;
-        uint32_t bits = 0;
-        if constexpr (needs_rng<C>::value) bits = sr_node_bits(p.sr_key, rb + xb + q);  // lattice-local node index
-        o0.v[q] = C::enc(drn, 0, bits);
-        o1.v[q] = C::enc(vx, 1, bits);
-        o2.v[q] = C::enc(vy, 2, bits);
-      }
-      const bool edge = !lt.xper && (xb == 0 || xb + KX >= lt.nx);  // holds an x wall or the ragged end
-      if (vec && !edge) {
-        *reinterpret_cast<RowVec2<E, KX>*>(d + rb + xb) = o0;
-        *reinterpret_cast<RowVec2<E, KX>*>(d + lt.plane + rb + xb) = o1;
-        *reinterpret_cast<RowVec2<E, KX>*>(d + 2 * lt.plane + rb + xb) = o2;
-      } else {
+        const int x = xb + q;
+        if (!lt.xper && (x == 0 || x == lt.nx - 1)) {
 #pragma unroll
-        for (int q = 0; q < KX; ++q) {
-          const int x = xb + q;
-          const bool wall = !lt.xper && (x == 0 || x == lt.nx - 1);
-          if (x < lt.nx && !wall) {
-            d[rb + x] = o0.v[q];
-            d[lt.plane + rb + x] = o1.v[q];
-            d[2 * lt.plane + rb + x] = o2.v[q];
-          }
+          for (int f = 0; f < 3; ++f) o[f].v[q] = prev[f].v[q];
         }
+      }
+      const int off = STORE && xb < lt.nx ? rb + xb * EB : kOutOfRange;
+#pragma unroll
+      for (int f = 0; f < 3; ++f) buf_store<V>(o[f], rd[f], off);
+    } else {
+#pragma unroll
+      for (int q = 0; q < KX; ++q) {
+        const int x = xb + q;
+        const bool node = STORE && x < lt.nx && (lt.xper || (x != 0 && x != lt.nx - 1));
+        const int off = node ? rb + x * EB : kOutOfRange;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) buf_store<E>(o[f].v[q], rd[f], off);
       }
     }
   };
 
-  load_row(y0 - 1);
-  for (int ys = y0 - 1; ys <= y1; ys += 3) {
-    source_row(ys, A0, A1, A2);
+  using NoStore = std::integral_constant<bool, false>;
+  using Store = std::integral_constant<bool, true>;
+  // source rows y0-1 .. y1 (y1 >= y0 + 1); the first two complete no row of
+  // the band
+  load_row(y0 - 1, true, ring[0], hring[0]);
+  load_row(y0, true, ring[1], hring[1]);
+  load_row(y0 + 1, true, ring[2], hring[2]);
+#pragma unroll
+  for (int f = 0; f < 3; ++f) cur[f] = ring[0][f];
+  source_row(NoStore{}, y0 - 1, A0, A1, A2, ring[0], hring[0]);
+  source_row(NoStore{}, y0, A1, A2, A0, ring[1], hring[1]);
+  for (int ys = y0 + 1; ys <= y1; ys += 3) {
+    source_row(Store{}, ys, A2, A0, A1, ring[2], hring[2]);
     if (ys + 1 > y1) break;
-    source_row(ys + 1, A1, A2, A0);
+    source_row(Store{}, ys + 1, A0, A1, A2, ring[0], hring[0]);
     if (ys + 2 > y1) break;
-    source_row(ys + 2, A2, A0, A1);
+    source_row(Store{}, ys + 2, A1, A2, A0, ring[1], hring[1]);
   }
 }
 
 // ------------------------------------------------------------------ launch
 bool fast2d_supported(const Layout& L, const StepParams& p) {
   if (L.q != 9 || L.ny < 3) return false;
+  if (L.plane * L.bytes >= (int64_t(1) << 31)) return false;  // buffer offsets are 31-bit
   // periodic x: whole segments only (the extent a multiple of 64)
   if (!p.fixed[0]) return L.nx % 64 == 0;
   return L.nx >= 3;
@@ -319,35 +360,34 @@ int fast2d_candidates(const Layout& L, const StepParams& p, int cus, Fast2DShape
   return n;
 }
 
-template <class C, int KX>
+template <class C, int KX, bool VEC>
 static hipError_t launch2d_kx(const void* src, void* dst, const Fast2DParams& fp, hipStream_t s) {
   using E = typename C::elem;
   const unsigned blocks = (unsigned)((fp.nitems + 3) / 4);
-  hipLaunchKernelGGL((step_d2q9_fast<C, KX>), dim3(blocks), dim3(256), 0, s, (const E*)src, (E*)dst, fp);
+  hipLaunchKernelGGL((step_d2q9_fast<C, KX, VEC>), dim3(blocks), dim3(256), 0, s, (const E*)src, (E*)dst, fp);
   return hipGetLastError();
 }
 
 template <class C>
-static hipError_t launch2d_codec(int kx, const void* src, void* dst, const Fast2DParams& fp, hipStream_t s) {
-  switch (kx) {
-    case 1: return launch2d_kx<C, 1>(src, dst, fp, s);
-    case 2: return launch2d_kx<C, 2>(src, dst, fp, s);
-
-  }
+static hipError_t launch2d_codec(int kx, bool vec, const void* src, void* dst, const Fast2DParams& fp,
+                                 hipStream_t s) {
+  if (kx == 1) return launch2d_kx<C, 1, true>(src, dst, fp, s);
+  if (kx == 2) return vec ? launch2d_kx<C, 2, true>(src, dst, fp, s) : launch2d_kx<C, 2, false>(src, dst, fp, s);
   return hipErrorInvalidValue;
 }
 
-static hipError_t launch2d(int precision, int kx, const void* src, void* dst, const Fast2DParams& fp, hipStream_t s) {
+static hipError_t launch2d(int precision, int kx, bool vec, const void* src, void* dst, const Fast2DParams& fp,
+                           hipStream_t s) {
   switch (precision) {
-    case MACLAB_FP64: return launch2d_codec<CodecF64>(kx, src, dst, fp, s);
-    case MACLAB_FP32: return launch2d_codec<CodecF32>(kx, src, dst, fp, s);
-    case MACLAB_HILO: return launch2d_codec<CodecHILO>(kx, src, dst, fp, s);
-    case MACLAB_S16: return launch2d_codec<CodecS16>(kx, src, dst, fp, s);
+    case MACLAB_FP64: return launch2d_codec<CodecF64>(kx, vec, src, dst, fp, s);
+    case MACLAB_FP32: return launch2d_codec<CodecF32>(kx, vec, src, dst, fp, s);
+    case MACLAB_HILO: return launch2d_codec<CodecHILO>(kx, vec, src, dst, fp, s);
+    case MACLAB_S16: return launch2d_codec<CodecS16>(kx, vec, src, dst, fp, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_step_fast2d_items(int precision, int kx, const void* src, void* dst, const Lattice2D* lat,
+hipError_t launch_step_fast2d_items(int precision, int kx, bool vec, const void* src, void* dst, const Lattice2D* lat,
                                     const int4* items, int nitems, double rho_ref, uint32_t sr_key, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   Fast2DParams fp{};
@@ -358,7 +398,7 @@ hipError_t launch_step_fast2d_items(int precision, int kx, const void* src, void
   fp.nband = 1;
   fp.rho_ref = rho_ref;
   fp.sr_key = sr_key;
-  return launch2d(precision, kx, src, dst, fp, s);
+  return launch2d(precision, kx, vec, src, dst, fp, s);
 }
 
 hipError_t launch_step_fast2d(const Layout& L, const void* src, void* dst, const StepParams& p,
@@ -385,7 +425,7 @@ hipError_t launch_step_fast2d(const Layout& L, const void* src, void* dst, const
   fp.nitems = fp.nseg * fp.nband;
   fp.rho_ref = p.rho_ref;
   fp.sr_key = p.sr_key;
-  return launch2d(L.precision, sh.kx, src, dst, fp, s);
+  return launch2d(L.precision, sh.kx, lt.aligned != 0, src, dst, fp, s);
 }
 
 }  // namespace maclab

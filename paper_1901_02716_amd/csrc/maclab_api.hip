@@ -740,6 +740,7 @@ struct maclab_batch_s {
   int64_t max_items = 0;
   int kx = 1, rows = 16;
   int nitems = 0;
+  int nvec = 0;                  // the first nvec items belong to lattices with aligned rows
   bool uploaded = false;
   int up_kx = 0, up_rows = 0;
   std::vector<Lattice2D> table_host;
@@ -864,8 +865,12 @@ int batch_plan(maclab_batch_t b, int kx, int rows, std::vector<Lattice2D>* table
     }
   }
   if ((int64_t)items->size() > b->max_items) return bfail(b, MACLAB_EINVAL, "too many work items for the workspace");
-  // largest items first, so the tail of the launch is made of small ones
+  // items of lattices with aligned rows first (they run the vector-access
+  // kernel, the others a second launch); in each group the largest items
+  // first, so the tail of a launch is made of small ones
   std::stable_sort(items->begin(), items->end(), [&](const int4& a, const int4& c) {
+    const int va = (*table)[a.x].aligned, vc = (*table)[c.x].aligned;
+    if (va != vc) return va > vc;
     const int64_t wa = std::min(64 * kx, (*table)[a.x].nx - a.y), wc = std::min(64 * kx, (*table)[c.x].nx - c.y);
     return (int64_t)(a.w - a.z) * wa > (int64_t)(c.w - c.z) * wc;
   });
@@ -903,6 +908,8 @@ int batch_sync(maclab_batch_t b) {
                                hipMemcpyHostToDevice, b->stream));
   BHIP_TRY(b, hipStreamSynchronize(b->stream));  // the host copies may change before the next sync
   b->nitems = (int)b->items_host.size();
+  b->nvec = 0;
+  while (b->nvec < b->nitems && b->table_host[b->items_host[b->nvec].x].aligned) ++b->nvec;
   b->uploaded = true;
   b->up_kx = b->kx;
   b->up_rows = b->rows;
@@ -925,8 +932,10 @@ void batch_advance(maclab_batch_t b, int64_t n) {
 
 int batch_launch(maclab_batch_t b, hipStream_t s, int cur, int64_t step) {
   const uint32_t key = sr_key(b->seed, (uint64_t)step);
-  BHIP_TRY(b, launch_step_fast2d_items(b->precision, b->kx, b->state[cur], b->state[cur ^ 1], b->table, b->items,
-                                       b->nitems, b->rho_ref, key, s));
+  BHIP_TRY(b, launch_step_fast2d_items(b->precision, b->kx, true, b->state[cur], b->state[cur ^ 1], b->table,
+                                       b->items, b->nvec, b->rho_ref, key, s));
+  BHIP_TRY(b, launch_step_fast2d_items(b->precision, b->kx, false, b->state[cur], b->state[cur ^ 1], b->table,
+                                       b->items + b->nvec, b->nitems - b->nvec, b->rho_ref, key, s));
   return MACLAB_OK;
 }
 

@@ -1,0 +1,136 @@
+"""GPU runs against long oracle runs stored under tests/golden/ (written by
+tests/golden/make_references.py from the FP64 oracle only).
+
+* 64^3 lid-driven cube at Re = 98.8 (the lattice Reynolds number of the
+  256^3 Re = 400 cube), 5000 steps: every 4th node per axis, the centre-line
+  profile and the diagnostics.
+* 64^3 cube at the literal Re = 400 (lid Mach 1.06): the step at which the
+  state first holds a non-finite value, and max |u|/e every 10 steps.
+* 1024^2 cavity at Re = 1000: every 16th node per axis, centre-line profiles
+  and diagnostics after 1000, 5000, 20000 and 50000 steps (those present).
+
+Tolerances (relative L2 over the stored nodes, physical units; kinetic
+energy relative; centre lines as RMS error over the lid speed): FP64 storage
+1e-12, FP32 1e-5, HILO and S16 2e-3; for the 1024^2 cavity these hold at
+1000 steps and grow as sqrt(steps / 1000) after that (rounding differences of
+two correct evaluations accumulate as a random walk).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1901_02716_amd import Simulation, workloads
+from conftest import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "hilo": 2e-3, "s16": 2e-3}
+
+
+def _sim(case, precision, seed=3):
+    sim = Simulation(case.q, case.n, case.dx, case.nu, precision=precision, seed=seed)
+    sim.set_fields(case.rho, case.u)
+    for face, (rb, ub) in case.fixed.items():
+        sim.set_bc(face, rb, ub)
+    return sim
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "hilo", "s16"])
+def test_cube64_5000_steps(precision):
+    ref = np.load(os.path.join(GOLD, "cube64_re98.8.npz"))
+    case = workloads.cavity_3d(n=64, Re=98.8, U=0.1)
+    steps = int(ref["steps"])
+    print(f"[ref] cube64 Re 98.8 {precision} {steps} steps", flush=True)
+    sim = _sim(case, precision)
+    sim.step(steps)
+    rho, u = sim.fields()
+    s = int(ref["stride"])
+    eu = rel_l2(u[:, ::s, ::s, ::s], ref["u"])
+    er = rel_l2(rho[::s, ::s, ::s], ref["rho"])
+    c = case.n[0] // 2
+    ec = rel_l2(0.5 * (u[0, :, c - 1, c - 1] + u[0, :, c, c]), ref["centre_ux"])
+    print(f"  relL2 u={eu:.2e} rho={er:.2e} centre={ec:.2e}", flush=True)
+    assert eu < TOL[precision] and er < TOL[precision] and ec < TOL[precision]
+    d = sim.diagnostics()
+    assert d[6] == 0
+    assert d[0] == pytest.approx(ref["diagnostics"][0], rel=TOL[precision])
+
+
+def test_cube64_re400_instability_matches_oracle():
+    """FP64: max |u|/e follows the oracle's trace while the flow is still
+    smooth (steps 10-70; the lid itself sits at |u|/e = 1.06), then blows up
+    between steps 70 and 80 as the oracle's does, and finally holds non-finite
+    values. Once |u|/e is in the thousands, rounding differences grow
+    exponentially, so the step of the first non-finite value is reported, not
+    compared."""
+    ref = json.load(open(os.path.join(GOLD, "cube64_re400.json")))
+    trace = dict((int(k), v) for k, v in ref["max_u_over_e_every_10_steps"])
+    case = workloads.cavity_3d(n=64, Re=400.0, U=0.1)
+    sim = _sim(case, "fp64")
+    for step in range(10, 71, 10):
+        sim.step(10)
+        assert sim.diagnostics()[5] == pytest.approx(trace[step], rel=1e-9), step
+    sim.step(10)
+    d = sim.diagnostics()
+    assert d[6] > 0 or d[5] > 1e3
+    assert trace[80] > 1e3
+    first, step = None, 80
+    while step < 3000:
+        sim.step(10)
+        step += 10
+        if sim.diagnostics()[6] > 0:
+            first = step
+            break
+    print(f"  first non-finite state within 10 steps before: GPU {first}, oracle {ref['first_nonfinite_step']}",
+          flush=True)
+    assert first is not None
+
+
+def _cavity_checkpoints():
+    path = os.path.join(GOLD, "cavity1024_re1000.npz")
+    if not os.path.exists(path):
+        return []
+    z = np.load(path)
+    return sorted(int(k.split("_")[1]) for k in z.files if k.startswith("diag_"))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_cavity1024_against_stored_oracle(precision):
+    marks = _cavity_checkpoints()
+    if not marks:
+        pytest.skip("cavity reference not generated")
+    ref = np.load(os.path.join(GOLD, "cavity1024_re1000.npz"))
+    case = workloads.cavity_2d(n=1024, Re=1000.0, U=0.1)
+    sim = _sim(case, precision)
+    done = 0
+    c = case.n[0] // 2
+    s = int(ref["stride"])
+    for m in marks:
+        print(f"[ref] cavity1024 {precision} to step {m}", flush=True)
+        sim.step(m - done)
+        done = m
+        rho, u = sim.fields()
+        eu = rel_l2(u[:, 0, ::s, ::s], ref[f"u_sub_{m}"])
+        er = rel_l2(rho[0, ::s, ::s], ref[f"rho_sub_{m}"])
+        ex = rel_l2(0.5 * (u[0, 0, :, c - 1] + u[0, 0, :, c]), ref[f"ux_centre_{m}"])
+        ey = rel_l2(0.5 * (u[1, 0, c - 1, :] + u[1, 0, c, :]), ref[f"uy_centre_{m}"])
+        d = sim.diagnostics()
+        ek = abs(d[4] - ref[f"diag_{m}"][4]) / abs(ref[f"diag_{m}"][4])
+        print(f"  step {m}: relL2 u={eu:.2e} rho={er:.2e} KE={ek:.2e}; centre lines relL2 ux(y)={ex:.2e} "
+              f"uy(x)={ey:.2e}", flush=True)
+        # Two correct evaluations of the step round differently in every step
+        # (the GPU sums deviations from rho_ref in another order than the
+        # oracle), and those differences accumulate like a random walk: the
+        # bar is the tolerance at 1000 steps, growing as sqrt(steps / 1000).
+        tol = TOL[precision] * max(1.0, np.sqrt(m / 1000.0))
+        assert max(eu, er, ek) < tol
+        # the centre lines in units of the lid speed (early on, u_y(x) is far
+        # smaller than the lid speed, so its own relative error says little)
+        U = 0.1
+        for got, want in ((0.5 * (u[0, 0, :, c - 1] + u[0, 0, :, c]), ref[f"ux_centre_{m}"]),
+                          (0.5 * (u[1, 0, c - 1, :] + u[1, 0, c, :]), ref[f"uy_centre_{m}"])):
+            assert np.sqrt(np.mean((got - want) ** 2)) / U < tol
