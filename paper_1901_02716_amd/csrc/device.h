@@ -143,6 +143,31 @@ struct needs_rng { static constexpr bool value = false; };
 template <>
 struct needs_rng<CodecS16> { static constexpr bool value = true; };
 
+// ----------------------------------------------------------- reciprocal
+// 1/x in FP32: the hardware estimate (v_rcp_f32, up to 1 ulp off, and not
+// symmetric about the exact value) refined by one Newton step, so that the
+// error stays within about half an ulp and does not build up as a drift over
+// many steps of u~ = m / rho.
+__device__ __forceinline__ float recip_f32(float x) {
+#pragma clang fp contract(off)
+  const float r = __builtin_amdgcn_rcpf(x);
+  const float e = __builtin_fmaf(-x, r, 1.0f);
+  return __builtin_fmaf(r, e, r);
+}
+
+// x / 36 for the link sums, which carry the weights times 36: the product
+// with the rounded constant 1/36 (which is 2.4e-8 too large in FP32) is
+// corrected by one residual step, so that no bias of that size is applied to
+// the density in every step.
+template <class T>
+__device__ __forceinline__ T div36(T x) {
+#pragma clang fp contract(off)
+  const T c = (T)(1.0 / 36.0);
+  const T q = x * c;
+  const T e = __builtin_fma((T)-36, q, x);
+  return __builtin_fma(e, c, q);
+}
+
 // ------------------------------------------------------ cross-lane moves
 // DPP wave rotates: lane l receives the value of lane l-1 (lane 0 that of
 // lane 63), or of lane l+1 (lane 63 that of lane 0).

@@ -248,14 +248,16 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src, typename C::elem* 
     V o[3];
 #pragma unroll
     for (int q = 0; q < KX; ++q) {
-      const T drn = am.r[q] * (T)(1.0 / 36.0);
+      // drho' = r / 36, u~' = (m / 36 + g) / (rho_ref + r / 36) = (m + 36 g) / (36 rho_ref + r)
+      const T drn = div36(am.r[q]);
+      const T den = (T)36 * rho_ref + am.r[q];
       T inv;
       if constexpr (sizeof(T) == 4)
-        inv = __builtin_amdgcn_rcpf(rho_ref + drn);  // v_rcp_f32, 1 ulp
+        inv = recip_f32(den);
       else
-        inv = (T)1 / (rho_ref + drn);
-      const T vx = __builtin_fma(am.mx[q], (T)(1.0 / 36.0), (T)lt.gx) * inv;
-      const T vy = __builtin_fma(am.my[q], (T)(1.0 / 36.0), (T)lt.gy) * inv;
+        inv = (T)1 / den;
+      const T vx = (am.mx[q] + (T)(36.0 * lt.gx)) * inv;
+      const T vy = (am.my[q] + (T)(36.0 * lt.gy)) * inv;
       uint32_t bits = 0;
       if constexpr (needs_rng<C>::value) bits = sr_node_bits(p.sr_key, (int64_t)lt.pitch * ywrap(yd) + xb + q);
       o[0].v[q] = C::enc(drn, 0, bits);

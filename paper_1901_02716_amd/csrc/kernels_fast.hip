@@ -30,7 +30,8 @@ struct Fast3DParams {
   int yper, zper, xwall;
   int nyb, nzb, nblocks;   // workgroups along y and z, total
   int64_t plane;           // elements per field plane
-  float rho_ref, gx, gy, gz;
+  float rho_ref;
+  float g36x, g36y, g36z;  // 36 dt G / e
   uint32_t sr_key;         // S16 rounding key of this step
 };
 
@@ -368,12 +369,12 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
       float r[KX], vx[KX], vy[KX], vz[KX];
 #pragma unroll
       for (int e = 0; e < KX; ++e) {
-        const float drn = am.r[e] * (1.f / 36.f);
-        const float inv = __builtin_amdgcn_rcpf(p.rho_ref + drn);  // v_rcp_f32, 1 ulp
-        r[e] = drn;
-        vx[e] = __builtin_fmaf(am.mx[e], 1.f / 36.f, p.gx) * inv;
-        vy[e] = __builtin_fmaf(am.my[e], 1.f / 36.f, p.gy) * inv;
-        vz[e] = __builtin_fmaf(am.mz[e], 1.f / 36.f, p.gz) * inv;
+        // drho' = r / 36, u~' = (m + 36 g) / (36 rho_ref + r)
+        const float inv = recip_f32(36.f * p.rho_ref + am.r[e]);
+        r[e] = div36(am.r[e]);
+        vx[e] = (am.mx[e] + p.g36x) * inv;
+        vy[e] = (am.my[e] + p.g36y) * inv;
+        vz[e] = (am.mz[e] + p.g36z) * inv;
       }
       const int64_t node0 = nx * ((int64_t)yrow + (int64_t)p.ny * zwrap(zd)) + xbase;
       uint32_t bits[KX];
@@ -512,12 +513,12 @@ __global__ __launch_bounds__(64 * NWV) void step_d3q19_indep(const typename C::e
       float r[KX], vx[KX], vy[KX], vz[KX];
 #pragma unroll
       for (int e = 0; e < KX; ++e) {
-        const float drn = am.r[e] * (1.f / 36.f);
-        const float inv = __builtin_amdgcn_rcpf(p.rho_ref + drn);  // v_rcp_f32, 1 ulp
-        r[e] = drn;
-        vx[e] = __builtin_fmaf(am.mx[e], 1.f / 36.f, p.gx) * inv;
-        vy[e] = __builtin_fmaf(am.my[e], 1.f / 36.f, p.gy) * inv;
-        vz[e] = __builtin_fmaf(am.mz[e], 1.f / 36.f, p.gz) * inv;
+        // drho' = r / 36, u~' = (m + 36 g) / (36 rho_ref + r)
+        const float inv = recip_f32(36.f * p.rho_ref + am.r[e]);
+        r[e] = div36(am.r[e]);
+        vx[e] = (am.mx[e] + p.g36x) * inv;
+        vy[e] = (am.my[e] + p.g36y) * inv;
+        vz[e] = (am.mz[e] + p.g36z) * inv;
       }
       const int64_t node0 = nx * ((int64_t)y + (int64_t)p.ny * zwrap(zd)) + xbase;
       uint32_t bits[KX];
@@ -711,9 +712,9 @@ hipError_t launch_step_fast(const Layout& L, const void* src, void* dst, const S
   }
   fp.plane = L.plane;
   fp.rho_ref = (float)p.rho_ref;
-  fp.gx = (float)p.g[0];
-  fp.gy = (float)p.g[1];
-  fp.gz = (float)p.g[2];
+  fp.g36x = (float)(36.0 * p.g[0]);
+  fp.g36y = (float)(36.0 * p.g[1]);
+  fp.g36z = (float)(36.0 * p.g[2]);
   fp.sr_key = p.sr_key;
   switch (L.precision) {
     case MACLAB_FP32: return launch_fast_codec<CodecF32>(L, sh, src, dst, fp, s);

@@ -64,21 +64,22 @@ __global__ __launch_bounds__(256) void step_generic_kernel(const typename C::ele
     const T rho = rho_ref + dr;
     const T cu = (T)cx * ux + (T)cy * uy + (T)cz * uz;
     const T uu = ux * ux + uy * uy + uz * uz;
-    const T w = (T)Lat::wnum[a] / (T)36;
-    const T F = w * (dr + rho * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu));
+    // 36 F^_a with the integer weight numerators (w_a = wnum_a / 36)
+    const T F = (T)Lat::wnum[a] * (dr + rho * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu));
     drho += F;
     if (cx) mx += (T)cx * F;
     if (cy) my += (T)cy * F;
     if (cz) mz += (T)cz * F;
   }
-  const T inv = (T)1 / (rho_ref + drho);
+  // drho' = r / 36, u~' = (m + 36 g) / (36 rho_ref + r)
+  const T inv = (T)1 / ((T)36 * rho_ref + drho);
   const int64_t x = i + p.nx * (j + p.ny * k);
   uint32_t bits = 0;
   if constexpr (needs_rng<C>::value) bits = sr_node_bits(p.sr_key, x);
-  store_field<C>(dst, p.plane, 0, x, drho, bits);
-  store_field<C>(dst, p.plane, 1, x, (mx + (T)p.g[0]) * inv, bits);
-  store_field<C>(dst, p.plane, 2, x, (my + (T)p.g[1]) * inv, bits);
-  if constexpr (D == 3) store_field<C>(dst, p.plane, 3, x, (mz + (T)p.g[2]) * inv, bits);
+  store_field<C>(dst, p.plane, 0, x, div36(drho), bits);
+  store_field<C>(dst, p.plane, 1, x, (mx + (T)(36.0 * p.g[0])) * inv, bits);
+  store_field<C>(dst, p.plane, 2, x, (my + (T)(36.0 * p.g[1])) * inv, bits);
+  if constexpr (D == 3) store_field<C>(dst, p.plane, 3, x, (mz + (T)(36.0 * p.g[2])) * inv, bits);
 }
 
 // Writes the fixed-face values into both buffers; a node on several fixed
