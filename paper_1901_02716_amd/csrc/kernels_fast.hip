@@ -21,6 +21,8 @@
 //    (neighbouring tiles share halo rows through that XCD's L2).
 #include "internal.h"
 
+#include <type_traits>
+
 namespace maclab {
 
 struct Fast3DParams {
@@ -301,12 +303,32 @@ struct RowData {
   float dr[KX], ux[KX], uy[KX], uz[KX];
 };
 
+// Raw (stored) elements of one row of the four fields.
+template <class C, int KX>
+struct RawRow {
+  RowVec<C, KX> f[4];
+};
+
 // PF: source planes loaded ahead (1 or 2).
+//
+// Memory goes through buffer resources of the four field planes, and every
+// wavefront of the workgroup -- output, halo or idle -- issues the same four
+// row loads and four row stores in every plane step: a wavefront without a
+// row to load or to store (a halo row never stores, an idle wave neither
+// loads nor stores, the first two planes of a tile complete no plane of it)
+// uses an out-of-range offset, so the load reads zero and the store is
+// dropped. With the same sequence of memory operations on every path the
+// compiler's wait for a plane's loads lets the previous plane's stores stay in
+// flight. Wall nodes of a stored row are written back with the raw values of
+// the source row of the same plane, loaded one step before.
 template <class C, int KX, int W, int PF>
 __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C::elem* __restrict__ src,
                                                                typename C::elem* __restrict__ dst, Fast3DParams p) {
+  using E = typename C::elem;
+  using V = RowVec<C, KX>;
   constexpr int NX = 64 * KX;
   constexpr int ROWS = W + 2;
+  constexpr int EB = (int)sizeof(E);
   __shared__ float lds[2 * ROWS * 5 * NX];
   const int lane = threadIdx.x;
   const int wv = threadIdx.y;
@@ -338,80 +360,120 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
     yrow = yrow < 0 ? 0 : (yrow > p.ny - 1 ? p.ny - 1 : yrow);
   const int xbase = lane * KX;
   const int64_t nx = NX;
-  const int64_t plane = p.plane;
 
+  buf_t rs[4], rd[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    rs[f] = make_buf(src + f * p.plane, p.plane * EB);
+    rd[f] = make_buf(dst + f * p.plane, p.plane * EB);
+  }
   auto zwrap = [&](int z) { return p.zper ? (z + p.nz) % p.nz : z; };
-  auto load_plane = [&](int z, RowData<KX>& b) {
-    const int64_t base = nx * ((int64_t)yrow + (int64_t)p.ny * zwrap(z)) + xbase;
-    load_row<C, KX>(src + base, 0, b.dr);
-    load_row<C, KX>(src + plane + base, 1, b.ux);
-    load_row<C, KX>(src + 2 * plane + base, 2, b.uy);
-    load_row<C, KX>(src + 3 * plane + base, 3, b.uz);
+  auto row_off = [&](int z) { return (int)((nx * ((int64_t)yrow + (int64_t)p.ny * zwrap(z)) + xbase) * EB); };
+  auto load_plane = [&](int z, bool valid, RawRow<C, KX>& b) {
+    const int off = valid && mode != 3 ? row_off(z) : kOutOfRange;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) b.f[f] = buf_load<V>(rs[f], off);
   };
+  const bool wall_lane = p.xwall && (lane == 0 || lane == 63);
+  // raw wall elements (element 0 of lane 0, element KX-1 of lane 63) of the
+  // row being pushed and of the row pushed one step before
+  E wcur[4], wprev[4];
 
   // One source plane: push its links, exchange the c_y = +-1 links through
-  // LDS, then finalise destination plane zs-1. am / ac / ap are the
-  // accumulators of destination planes zs-1, zs, zs+1; b holds plane zs and
-  // is refilled with plane zs+PF.
-  auto source_plane = [&](int zs, PlaneAcc<KX>& am, PlaneAcc<KX>& ac, PlaneAcc<KX>& ap, RowData<KX>& b) {
+  // LDS, then finalise destination plane zs-1 (STORE) or issue the same stores
+  // out of range. am / ac / ap are the accumulators of destination planes
+  // zs-1, zs, zs+1; b holds plane zs and is refilled with plane zs+PF.
+  auto source_plane = [&](auto store_c, int zs, PlaneAcc<KX>& am, PlaneAcc<KX>& ac, PlaneAcc<KX>& ap,
+                          RawRow<C, KX>& b) {
+    constexpr bool STORE = decltype(store_c)::value;
+    float dr[KX], ux[KX], uy[KX], uz[KX];
+#pragma unroll
+    for (int e = 0; e < KX; ++e) {
+      dr[e] = (float)C::dec(b.f[0].v[e], 0);
+      ux[e] = (float)C::dec(b.f[1].v[e], 1);
+      uy[e] = (float)C::dec(b.f[2].v[e], 2);
+      uz[e] = (float)C::dec(b.f[3].v[e], 3);
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      wprev[f] = wcur[f];
+      wcur[f] = lane == 0 ? b.f[f].v[0] : b.f[f].v[KX - 1];
+    }
     if (mode == 0)
-      push_row<KX, 0>(b.dr, b.ux, b.uy, b.uz, p.rho_ref, am, ac, ap, up, dn, lane);
+      push_row<KX, 0>(dr, ux, uy, uz, p.rho_ref, am, ac, ap, up, dn, lane);
     else if (mode == 1)
-      push_row<KX, 1>(b.dr, b.ux, b.uy, b.uz, p.rho_ref, am, ac, ap, up, dn, lane);
+      push_row<KX, 1>(dr, ux, uy, uz, p.rho_ref, am, ac, ap, up, dn, lane);
     else if (mode == 2)
-      push_row<KX, 2>(b.dr, b.ux, b.uy, b.uz, p.rho_ref, am, ac, ap, up, dn, lane);
-    if (zs + PF <= z1 && mode != 3) load_plane(zs + PF, b);
+      push_row<KX, 2>(dr, ux, uy, uz, p.rho_ref, am, ac, ap, up, dn, lane);
+    load_plane(zs + PF, zs + PF <= z1, b);
     __syncthreads();
     if (out_row) pull_rows<KX>(from_below, from_above, am, ac, ap, lane);
     __syncthreads();
     const int zd = zs - 1;
-    if (out_row && zd >= z0) {
-      float r[KX], vx[KX], vy[KX], vz[KX];
+    V o[4] = {};
+    if (STORE && out_row) {
 #pragma unroll
       for (int e = 0; e < KX; ++e) {
         // drho' = r / 36, u~' = (m + 36 g) / (36 rho_ref + r)
         const float inv = recip_f32(36.f * p.rho_ref + am.r[e]);
-        r[e] = div36(am.r[e]);
-        vx[e] = (am.mx[e] + p.g36x) * inv;
-        vy[e] = (am.my[e] + p.g36y) * inv;
-        vz[e] = (am.mz[e] + p.g36z) * inv;
+        const float r = div36(am.r[e]);
+        const float vx = (am.mx[e] + p.g36x) * inv;
+        const float vy = (am.my[e] + p.g36y) * inv;
+        const float vz = (am.mz[e] + p.g36z) * inv;
+        uint32_t bits = 0;
+        if constexpr (needs_rng<C>::value)
+          bits = sr_node_bits(p.sr_key, nx * ((int64_t)yrow + (int64_t)p.ny * zwrap(zd)) + xbase + e);
+        o[0].v[e] = C::enc(r, 0, bits);
+        o[1].v[e] = C::enc(vx, 1, bits);
+        o[2].v[e] = C::enc(vy, 2, bits);
+        o[3].v[e] = C::enc(vz, 3, bits);
       }
-      const int64_t node0 = nx * ((int64_t)yrow + (int64_t)p.ny * zwrap(zd)) + xbase;
-      uint32_t bits[KX];
+      if (wall_lane) {
 #pragma unroll
-      for (int e = 0; e < KX; ++e) bits[e] = needs_rng<C>::value ? sr_node_bits(p.sr_key, node0 + e) : 0u;
-      store_row<C, KX>(dst + node0, 0, r, bits, lane, p.xwall);
-      store_row<C, KX>(dst + plane + node0, 1, vx, bits, lane, p.xwall);
-      store_row<C, KX>(dst + 2 * plane + node0, 2, vy, bits, lane, p.xwall);
-      store_row<C, KX>(dst + 3 * plane + node0, 3, vz, bits, lane, p.xwall);
+        for (int f = 0; f < 4; ++f) {
+          if (lane == 0)
+            o[f].v[0] = wprev[f];
+          else
+            o[f].v[KX - 1] = wprev[f];
+        }
+      }
     }
+    const int off = STORE && out_row ? row_off(zd) : kOutOfRange;
+    // the new state is not read again in this step: stream it past the caches
+#pragma unroll
+    for (int f = 0; f < 4; ++f) buf_store<V, 2>(o[f], rd[f], off);
   };
 
-  // source planes z0-1 .. z1; six per trip so that the accumulator roles
-  // (period 3) and the prefetch buffers (period PF) rotate at compile time.
-  // The destination planes z0-2 and z0-1 start from zero; plane zs+1 is
-  // assigned by the push of plane zs.
+  // Source planes z0-1 .. z1 (z1 >= z0 + 1); the first two complete no plane
+  // of the tile. Accumulator roles rotate with period 3 and the prefetch
+  // buffers with period PF, so six planes per trip. The destination planes
+  // z0-2 and z0-1 start from zero; plane zs+1 is assigned by the push of
+  // plane zs.
+  using NoStore = std::integral_constant<bool, false>;
+  using Store = std::integral_constant<bool, true>;
   PlaneAcc<KX> a0, a1, a2;
   a0.zero();
   a1.zero();
-  RowData<KX> b0, b1;
-  if (mode != 3) {
-    load_plane(z0 - 1, b0);
-    if (PF == 2) load_plane(z0, b1);
-  }
-  RowData<KX>& c1 = PF == 2 ? b1 : b0;
-  for (int zs = z0 - 1; zs <= z1; zs += 6) {
-    source_plane(zs, a0, a1, a2, b0);
+  RawRow<C, KX> b0, b1;
+  load_plane(z0 - 1, true, b0);
+  if constexpr (PF == 2) load_plane(z0, true, b1);
+  RawRow<C, KX>& c1 = PF == 2 ? b1 : b0;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) wcur[f] = E{};
+  source_plane(NoStore{}, z0 - 1, a0, a1, a2, b0);
+  source_plane(NoStore{}, z0, a1, a2, a0, c1);
+  for (int zs = z0 + 1; zs <= z1; zs += 6) {
+    source_plane(Store{}, zs, a2, a0, a1, b0);
     if (zs + 1 > z1) break;
-    source_plane(zs + 1, a1, a2, a0, c1);
+    source_plane(Store{}, zs + 1, a0, a1, a2, c1);
     if (zs + 2 > z1) break;
-    source_plane(zs + 2, a2, a0, a1, b0);
+    source_plane(Store{}, zs + 2, a1, a2, a0, b0);
     if (zs + 3 > z1) break;
-    source_plane(zs + 3, a0, a1, a2, c1);
+    source_plane(Store{}, zs + 3, a2, a0, a1, c1);
     if (zs + 4 > z1) break;
-    source_plane(zs + 4, a1, a2, a0, b0);
+    source_plane(Store{}, zs + 4, a0, a1, a2, b0);
     if (zs + 5 > z1) break;
-    source_plane(zs + 5, a2, a0, a1, c1);
+    source_plane(Store{}, zs + 5, a1, a2, a0, c1);
   }
 }
 
@@ -554,6 +616,7 @@ bool fast_step_supported(const Layout& L, const StepParams& p) {
   if (L.precision != MACLAB_FP32 && L.precision != MACLAB_HILO && L.precision != MACLAB_S16) return false;
   if (L.nx != 64 && L.nx != 128 && L.nx != 256) return false;
   if (L.ny < 3 || L.nz < 3) return false;
+  if (L.plane * L.bytes >= (int64_t(1) << 31)) return false;  // buffer offsets are 31-bit
   (void)p;
   return true;
 }
