@@ -61,6 +61,7 @@ struct CodecF64 {
   static constexpr int bytes = 8;
   __device__ static T dec(elem s, int) { return s; }
   __device__ static elem enc(T v, int, uint32_t) { return v; }
+  __device__ static elem enc_nearest(T v, int field) { return enc(v, field, 0u); }
 };
 
 struct CodecF32 {
@@ -69,6 +70,7 @@ struct CodecF32 {
   static constexpr int bytes = 4;
   __device__ static T dec(elem s, int) { return s; }
   __device__ static elem enc(T v, int, uint32_t) { return v; }
+  __device__ static elem enc_nearest(T v, int field) { return enc(v, field, 0u); }
 };
 
 // Split bfloat16: hi = bf16(v), lo = bf16(v - hi), packed as (hi << 16) | lo
@@ -85,6 +87,7 @@ struct CodecHILO {
     const __bf16 lo = (__bf16)(v - (float)hi);
     return ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16) | (uint32_t)__builtin_bit_cast(uint16_t, lo);
   }
+  __device__ static elem enc_nearest(T v, int field) { return enc(v, field, 0u); }
 };
 
 // Scaled binary16 with stochastic rounding: the value times 2^10 (density
@@ -106,17 +109,23 @@ struct CodecS16 {
     _Float16 h = __builtin_bit_cast(_Float16, s);
     return (float)h * inv_scale(field);
   }
+  // Stochastic rounding by the hardware conversion (v_cvt_sr_f16_f32, which
+  // rounds up with probability equal to the discarded fraction, drawn from
+  // the high bits of its random operand); field f uses the node's 32 random
+  // bits rotated by 8 f.
   __device__ static elem enc(T v, int field, uint32_t node_bits) {
-    float x = v * scale(field);
-    uint32_t b = f32_bits(x);
-    const uint32_t r = ((node_bits >> (8 * field)) & 0xffu) << 5;
-    if ((b & 0x7f800000u) != 0x7f800000u) b = (b + r) & ~0x1fffu;
-    _Float16 h = (_Float16)bits_f32(b);
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const uint32_t r = field == 0 ? node_bits : ((node_bits << (8 * field)) | (node_bits >> (32 - 8 * field)));
+    h2 h = {};
+    h = __builtin_amdgcn_cvt_sr_f16_f32(h, v * scale(field), r, false);
+    return __builtin_bit_cast(uint16_t, h.x);
+  }
+  // Round to nearest (fields set from outside the time loop).
+  __device__ static elem enc_nearest(T v, int field) {
+    const _Float16 h = (_Float16)(v * scale(field));
     return __builtin_bit_cast(uint16_t, h);
   }
 };
-
-constexpr uint32_t kRoundNearestBits = 0x80808080u;
 
 // Counter-based random bits for CodecS16: a 32-bit integer finaliser of a
 // Weyl sequence over the node index, offset by a key that mixes the seed and

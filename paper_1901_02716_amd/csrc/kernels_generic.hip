@@ -99,8 +99,8 @@ __global__ void impose_bc_kernel(typename C::elem* b0, typename C::elem* b1, int
   }
   if (face < 0) return;
   typename C::elem v[4];
-  v[0] = C::enc((typename C::T)(fv.rho[face] - rho_ref), 0, kRoundNearestBits);
-  for (int c = 0; c < d; ++c) v[1 + c] = C::enc((typename C::T)(fv.u[face][c] / e), 1 + c, kRoundNearestBits);
+  v[0] = C::enc_nearest((typename C::T)(fv.rho[face] - rho_ref), 0);
+  for (int c = 0; c < d; ++c) v[1 + c] = C::enc_nearest((typename C::T)(fv.u[face][c] / e), 1 + c);
   for (int f = 0; f <= d; ++f) {
     b0[f * plane + x] = v[f];
     b1[f * plane + x] = v[f];
@@ -113,7 +113,7 @@ __global__ void encode_kernel(typename C::elem* dst, const double* __restrict__ 
                               double offset, double mul, int field) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
-  dst[i] = C::enc((typename C::T)((src[i] - offset) * mul), field, kRoundNearestBits);
+  dst[i] = C::enc_nearest((typename C::T)((src[i] - offset) * mul), field);
 }
 
 // Stored -> physical float64: dst = offset + mul * value.
