@@ -161,6 +161,47 @@ def time_adjoint(T: int, precision: str = "fp32", reps: int = 3):
     return out
 
 
+def time_batch(steps: int, sep_steps: int):
+    """512 D2Q9 lid-driven cavities of the seeded draw (N uniform in
+    [64, 512], Re log-uniform in [100, 5000], lid speed uniform in
+    [0.05, 0.1]; seed 4), FP32: aggregate MLUPS of one launch per step over
+    all cavities (HIP graphs, autotuned tiling) against one launch per cavity
+    per step."""
+    import torch
+
+    from paper_1901_02716_amd import cavities, workloads
+
+    draws = workloads.batch_draw()
+    b = cavities(draws, precision="fp32")
+    tune_ms = b.autotune(reps=3)
+    lu = b.updated_nodes()
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def timed(fn, n):
+        fn(2)
+        torch.cuda.synchronize()
+        a, c = ev(), ev()
+        a.record(b.stream)
+        fn(n)
+        c.record(b.stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(c) / n
+
+    ms = timed(b.step, steps)
+    ms_sep = timed(b.step_separate, sep_steps)
+    nonfinite = sum(1 for i in range(len(b)) if b[i].diagnostics()[6] > 0)
+    out = {"workload": "512 D2Q9 lid-driven cavities, seed 4 draw, FP32",
+           "nodes_per_step": sum(N * N for N, _, _ in draws), "updated_nodes_per_step": lu,
+           "mlups": round(lu / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 5),
+           "hbm_frac": round(24 * lu / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "separate_launches_mlups": round(lu / (ms_sep * 1e-3) / 1e6, 1),
+           "separate_ms_per_step": round(ms_sep, 5), "speedup_vs_separate": round(ms_sep / ms, 3),
+           "tiling": b.tiling(), "autotune_best_ms": round(tune_ms, 5),
+           "nonfinite_cavities_after": nonfinite, "steps_timed": steps}
+    b.close()
+    return out
+
+
 def cpu_baseline(case, steps: int):
     """The FP64 oracle on `steps` steps of the same lattice, one thread."""
     import oracle
@@ -198,12 +239,14 @@ def main(argv=None):
     ap.add_argument("--workload", default="cube256", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp32", choices=sorted(BYTES))
     ap.add_argument("--variants", default="s16,hilo", help="extra storage variants to time ('' for none)")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="use the default tiling")
     ap.add_argument("--tiling", default="", help="W,nyb,nzb,pf[,kernel] of the fast kernel (skips autotuning)")
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="T of the reverse-mode cost measurement (0 to skip)")
+    ap.add_argument("--batch-steps", type=int, default=200,
+                    help="steps of the 512-cavity batch measurement (0 to skip)")
     ap.add_argument("--profile-copy-mib", type=int, default=0,
                     help="after timing, run one torch copy of this many MiB (counter calibration)")
     args = ap.parse_args(argv)
@@ -242,6 +285,7 @@ def main(argv=None):
                        "hbm_frac": round(2 * (d + 1) * BYTES[v] * lu / (vms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     adjoint = time_adjoint(args.adjoint_steps) if args.adjoint_steps > 0 else None
+    batch = time_batch(args.batch_steps, max(10, args.batch_steps // 4)) if args.batch_steps > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -278,6 +322,7 @@ def main(argv=None):
         "cpu_baseline": cpu,
         "variants": variants,
         "adjoint": adjoint,
+        "batch": batch,
         "diagnostics_after": {"mass": diag[0], "max_u_over_e": diag[5], "nonfinite": diag[6]},
         "wall_s": round(wall, 3),
         "kernel_source_hash": kernel_source_hash(),

@@ -412,6 +412,10 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
     const int zd = zs - 1;
     V o[4] = {};
     if (STORE && out_row) {
+      // rounding bits of the row's nodes: one hash of the lane's first node,
+      // spread to its KX nodes by distinct odd constants
+      uint32_t hb = 0;
+      if constexpr (needs_rng<C>::value) hb = sr_node_bits(p.sr_key, nx * ((int64_t)yrow + (int64_t)p.ny * zwrap(zd)) + xbase);
 #pragma unroll
       for (int e = 0; e < KX; ++e) {
         // drho' = r / 36, u~' = (m + 36 g) / (36 rho_ref + r)
@@ -420,9 +424,7 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
         const float vx = (am.mx[e] + p.g36x) * inv;
         const float vy = (am.my[e] + p.g36y) * inv;
         const float vz = (am.mz[e] + p.g36z) * inv;
-        uint32_t bits = 0;
-        if constexpr (needs_rng<C>::value)
-          bits = sr_node_bits(p.sr_key, nx * ((int64_t)yrow + (int64_t)p.ny * zwrap(zd)) + xbase + e);
+        const uint32_t bits = hb ^ ((uint32_t)e * 0x9e3779b9u);
         o[0].v[e] = C::enc(r, 0, bits);
         o[1].v[e] = C::enc(vx, 1, bits);
         o[2].v[e] = C::enc(vy, 2, bits);
@@ -584,8 +586,9 @@ __global__ __launch_bounds__(64 * NWV) void step_d3q19_indep(const typename C::e
       }
       const int64_t node0 = nx * ((int64_t)y + (int64_t)p.ny * zwrap(zd)) + xbase;
       uint32_t bits[KX];
+      const uint32_t hb = needs_rng<C>::value ? sr_node_bits(p.sr_key, node0) : 0u;
 #pragma unroll
-      for (int e = 0; e < KX; ++e) bits[e] = needs_rng<C>::value ? sr_node_bits(p.sr_key, node0 + e) : 0u;
+      for (int e = 0; e < KX; ++e) bits[e] = hb ^ ((uint32_t)e * 0x9e3779b9u);  // as the exchange kernel
       store_row<C, KX>(dst + node0, 0, r, bits, lane, p.xwall);
       store_row<C, KX>(dst + plane + node0, 1, vx, bits, lane, p.xwall);
       store_row<C, KX>(dst + 2 * plane + node0, 2, vy, bits, lane, p.xwall);
