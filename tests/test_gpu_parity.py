@@ -220,11 +220,14 @@ def test_mismatched_faces_rejected():
     ("cube256_hilo", lambda: workloads.cavity_3d(n=256, Re=400.0, U=0.1), "hilo", 2e-3),
 ])
 def test_full_size_step_on_sampled_nodes(name, mk, precision, tol):
-    """At the benchmark sizes: after a few GPU steps, the next GPU step is
-    compared with the oracle's step from the same state on sampled nodes."""
+    """At the benchmark sizes and in the autotuned launch configuration the
+    benchmark times: after a few GPU steps, the next GPU step is compared with
+    the oracle's step from the same state on sampled nodes."""
     case = mk()
     print(f"[full-size] {name}", flush=True)
     sim = make_sim(case, precision)
+    sim.autotune(reps=3)  # the launch configuration the benchmark times
+    print(f"  tiling {sim.tiling()}", flush=True)
     sim.step(5)
     rho, u = sim.fields()
     sim.step(1)
