@@ -182,28 +182,23 @@ __device__ __forceinline__ void push_row(const float (&dr)[KX], const float (&ux
   float f0[KX], hzp[KX], hzm[KX];
   float hxp[KX], p0p[KX], p0m[KX];  // move to x+1
   float hxm[KX], m0p[KX], m0m[KX];  // move to x-1
+  // c_y = +1 links (to the next row) and c_y = -1 links (to the previous row)
+  float hyp[KX], pp0[KX], mp0[KX], zpp[KX], zpm[KX];
+  float hym[KX], pm0[KX], mm0[KX], zmp[KX], zmm[KX];
 #pragma unroll
   for (int e = 0; e < KX; ++e) {
     Links L;
     node_links(dr[e], ux[e], uy[e], uz[e], rho_ref, L);
-    // c_y = +1 links to the next row, c_y = -1 links to the previous row;
-    // LDS rows are stored transposed (node KX*l + e at e*64 + l) so that a
-    // wavefront touches 64 consecutive words
-    const int x = e * 64 + lane;
-    if constexpr (MODE != 2) {
-      up[0 * NX + x] = L.hyp;
-      up[1 * NX + x] = L.pp0;
-      up[2 * NX + x] = L.mp0;
-      up[3 * NX + x] = L.zpp;
-      up[4 * NX + x] = L.zpm;
-    }
-    if constexpr (MODE != 1) {
-      dn[0 * NX + x] = L.hym;
-      dn[1 * NX + x] = L.pm0;
-      dn[2 * NX + x] = L.mm0;
-      dn[3 * NX + x] = L.zmp;
-      dn[4 * NX + x] = L.zmm;
-    }
+    hyp[e] = L.hyp;
+    pp0[e] = L.pp0;
+    mp0[e] = L.mp0;
+    zpp[e] = L.zpp;
+    zpm[e] = L.zpm;
+    hym[e] = L.hym;
+    pm0[e] = L.pm0;
+    mm0[e] = L.mm0;
+    zmp[e] = L.zmp;
+    zmm[e] = L.zmm;
     f0[e] = L.f0;
     hzp[e] = L.hzp;
     hzm[e] = L.hzm;
@@ -214,6 +209,27 @@ __device__ __forceinline__ void push_row(const float (&dr)[KX], const float (&ux
     m0p[e] = L.m0p;
     m0m[e] = L.m0m;
   }
+  // What node x of the neighbouring row receives in the plane of the source
+  // (the axis link of node x, the +x-moving diagonal of node x-1 and the
+  // -x-moving one of node x+1) is combined here into its density and x
+  // momentum contributions s and d; the +-z diagonals go as they are. LDS rows
+  // are stored transposed (node KX*l + e at e*64 + l) so that a wavefront
+  // touches 64 consecutive words.
+  auto send = [&](float* __restrict__ buf, const float (&h)[KX], const float (&ep)[KX], const float (&em)[KX],
+                  const float (&vp)[KX], const float (&vm)[KX]) {
+    const float in_ep = from_left_lane(ep[KX - 1]), in_em = from_right_lane(em[0]);
+#pragma unroll
+    for (int e = 0; e < KX; ++e) {
+      const float a = e > 0 ? ep[e - 1] : in_ep, b = e < KX - 1 ? em[e + 1] : in_em;
+      const int x = e * 64 + lane;
+      buf[0 * NX + x] = __builtin_fmaf(2.f, h[e], a + b);
+      buf[1 * NX + x] = a - b;
+      buf[2 * NX + x] = vp[e];
+      buf[3 * NX + x] = vm[e];
+    }
+  };
+  if constexpr (MODE != 2) send(up, hyp, pp0, mp0, zpp, zpm);
+  if constexpr (MODE != 1) send(dn, hym, pm0, mm0, zmp, zmm);
   if constexpr (MODE == 0) own_row_links<KX>(f0, hzp, hzm, hxp, p0p, p0m, hxm, m0p, m0m, am, ac, ap);
 }
 
@@ -280,21 +296,42 @@ __device__ __forceinline__ void add_row_links(float h, float ep_from_left, float
   }
 }
 
-// Adds the links sent through LDS by the rows below and above.
+// Adds the contributions sent through LDS by the rows below (c_y = +1 links,
+// S = +1) and above (c_y = -1 links, S = -1): s and d in the plane of the
+// source, vp / vm moving to planes z+1 / z-1. The y momentum of plane z+1 is
+// first touched by the row below, so it is assigned.
+template <int KX, int S>
+__device__ __forceinline__ void add_sent(float s, float d, float vp, float vm, int e, PlaneAcc<KX>& am,
+                                         PlaneAcc<KX>& ac, PlaneAcc<KX>& ap) {
+#pragma clang fp contract(off)
+  ac.r[e] += s;
+  ac.mx[e] += d;
+  ap.r[e] += vp;
+  ap.mz[e] += vp;
+  am.r[e] += vm;
+  am.mz[e] -= vm;
+  if constexpr (S > 0) {
+    ac.my[e] += s;
+    ap.my[e] = vp;
+    am.my[e] += vm;
+  } else {
+    ac.my[e] -= s;
+    ap.my[e] -= vp;
+    am.my[e] -= vm;
+  }
+}
+
 template <int KX>
 __device__ __forceinline__ void pull_rows(const float* __restrict__ from_below, const float* __restrict__ from_above,
                                           PlaneAcc<KX>& am, PlaneAcc<KX>& ac, PlaneAcc<KX>& ap, int lane) {
   constexpr int NX = 64 * KX;
 #pragma unroll
   for (int e = 0; e < KX; ++e) {
-    // transposed positions of nodes x, x-1 and x+1 (periodic across the row)
     const int x = e * 64 + lane;
-    const int xl = e > 0 ? (e - 1) * 64 + lane : (KX - 1) * 64 + ((lane + 63) & 63);
-    const int xr = e < KX - 1 ? (e + 1) * 64 + lane : ((lane + 1) & 63);
-    add_row_links<KX, 1>(from_below[0 * NX + x], from_below[1 * NX + xl], from_below[2 * NX + xr],
-                         from_below[3 * NX + x], from_below[4 * NX + x], e, am, ac, ap);
-    add_row_links<KX, -1>(from_above[0 * NX + x], from_above[1 * NX + xl], from_above[2 * NX + xr],
-                          from_above[3 * NX + x], from_above[4 * NX + x], e, am, ac, ap);
+    add_sent<KX, 1>(from_below[0 * NX + x], from_below[1 * NX + x], from_below[2 * NX + x], from_below[3 * NX + x], e,
+                    am, ac, ap);
+    add_sent<KX, -1>(from_above[0 * NX + x], from_above[1 * NX + x], from_above[2 * NX + x], from_above[3 * NX + x], e,
+                     am, ac, ap);
   }
 }
 
@@ -329,13 +366,13 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
   constexpr int NX = 64 * KX;
   constexpr int ROWS = W + 2;
   constexpr int EB = (int)sizeof(E);
-  __shared__ float lds[2 * ROWS * 5 * NX];
+  __shared__ float lds[2 * ROWS * 4 * NX];
   const int lane = threadIdx.x;
   const int wv = threadIdx.y;
-  float* up = lds + wv * 5 * NX;               // this wave's c_y = +1 links
-  float* dn = lds + (ROWS + wv) * 5 * NX;      // this wave's c_y = -1 links
-  const float* from_below = lds + (wv > 0 ? wv - 1 : 0) * 5 * NX;
-  const float* from_above = lds + (ROWS + (wv + 1 < ROWS ? wv + 1 : wv)) * 5 * NX;
+  float* up = lds + wv * 4 * NX;               // what this wave's row sends to the next row
+  float* dn = lds + (ROWS + wv) * 4 * NX;      // ... and to the previous row
+  const float* from_below = lds + (wv > 0 ? wv - 1 : 0) * 4 * NX;
+  const float* from_above = lds + (ROWS + (wv + 1 < ROWS ? wv + 1 : wv)) * 4 * NX;
 
   // XCD-aware tile numbering: XCD k (= blockIdx.x mod 8) gets a contiguous band
   const int bid = blockIdx.x;
