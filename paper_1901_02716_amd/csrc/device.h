@@ -92,13 +92,9 @@ struct CodecHILO {
 
 // Scaled binary16 with stochastic rounding: the value times 2^10 (density
 // deviation) or 2^6 (velocity) is rounded to one of its two neighbouring
-// binary16 values with probability proportional to proximity. `node_bits`
-// holds one random byte per field (field f uses byte f): the byte is added
-// just below the 10-bit binary16 mantissa of the float32 value (bits 5..12 of
-// the 13 that binary16 drops), which is then truncated, so the conversion is
-// exact for results in the binary16 normal range and rounds up with
-// probability (dropped fraction) to within 2^-8 (smaller magnitudes round to
-// nearest). node_bits = 0x80808080 rounds every field to nearest.
+// binary16 values, up with probability equal to the fraction that binary16
+// drops. Each stored node draws 32 random bits per step (`node_bits`, from a
+// counter-based generator over the node index and the step).
 struct CodecS16 {
   using elem = uint16_t;
   using T = float;
@@ -168,13 +164,16 @@ __device__ __forceinline__ float recip_f32(float x) {
 // with the rounded constant 1/36 (which is 2.4e-8 too large in FP32) is
 // corrected by one residual step, so that no bias of that size is applied to
 // the density in every step.
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <class T>
 __device__ __forceinline__ T div36(T x) {
 #pragma clang fp contract(off)
   const T c = (T)(1.0 / 36.0);
   const T q = x * c;
-  const T e = __builtin_fma((T)-36, q, x);
-  return __builtin_fma(e, c, q);
+  const T e = fma_t((T)-36, q, x);
+  return fma_t(e, c, q);
 }
 
 // ------------------------------------------------------ cross-lane moves

@@ -49,15 +49,15 @@ __device__ __forceinline__ void links2(T dr, T ux, T uy, T rho_ref, Links2<T>& L
   const T r3 = (T)3 * rho;
   const T bx = r3 * ux, by = r3 * uy;
   const T cxx = bx * ux, cyy = by * uy, cxy = bx * uy;  // 3 rho u_i u_j
-  const T a = __builtin_fma(cxx + cyy, (T)-0.5, dr);
-  const T sx = __builtin_fma(cxx, (T)1.5, a), sy = __builtin_fma(cyy, (T)1.5, a);
+  const T a = fma_t(cxx + cyy, (T)-0.5, dr);
+  const T sx = fma_t(cxx, (T)1.5, a), sy = fma_t(cyy, (T)1.5, a);
   L.f0 = (T)16 * a;
   L.qxp = sx + bx;
   L.qxm = sx - bx;
   L.qyp = sy + by;
   L.qym = sy - by;
-  const T t = __builtin_fma(cyy, (T)1.5, sx);
-  const T p = __builtin_fma(cxy, (T)3, t), m = __builtin_fma(cxy, (T)-3, t);
+  const T t = fma_t(cyy, (T)1.5, sx);
+  const T p = fma_t(cxy, (T)3, t), m = fma_t(cxy, (T)-3, t);
   const T u = bx + by, v = bx - by;
   L.pp = p + u;
   L.mm = p - u;
@@ -193,15 +193,15 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src, typename C::elem* 
     T mq[KX], mmp[KX], mmm[KX];    // M links of node e: (-1,0)/4, (-1,1), (-1,-1)
     auto complete = [&](int q, T Pq, T Ppp, T Ppm, T Mq, T Mmp, T Mmm) {
       // row ys: rest, +-x
-      ac.r[q] += __builtin_fma((T)4, Pq + Mq, of0[q]);
-      ac.mx[q] = __builtin_fma((T)4, Pq - Mq, ac.mx[q]);
+      ac.r[q] += fma_t((T)4, Pq + Mq, of0[q]);
+      ac.mx[q] = fma_t((T)4, Pq - Mq, ac.mx[q]);
       // row ys+1: +y, +x+y, -x+y
-      const T sp = __builtin_fma((T)4, oyp[q], Ppp + Mmp);
+      const T sp = fma_t((T)4, oyp[q], Ppp + Mmp);
       ap.r[q] = sp;
       ap.my[q] = sp;
       ap.mx[q] = Ppp - Mmp;
       // row ys-1: -y, +x-y, -x-y
-      const T sm = __builtin_fma((T)4, oym[q], Ppm + Mmm);
+      const T sm = fma_t((T)4, oym[q], Ppm + Mmm);
       am.r[q] += sm;
       am.my[q] -= sm;
       am.mx[q] += Ppm - Mmm;

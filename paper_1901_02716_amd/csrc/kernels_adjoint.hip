@@ -250,9 +250,9 @@ __global__ __launch_bounds__(256) void adjoint_d2q9_fast(const typename C::elem*
         const T YL = e == 0 ? inMy : My[el], YR = e == KX - 1 ? inMyr : My[er];
         const T sP = PL + PR, dX = XR - XL, sY = YL + YR;
         a2[e] = sP + dX;
-        a0[e] = __builtin_fma((T)4, P[e], a2[e]);
+        a0[e] = fma_t((T)4, P[e], a2[e]);
         a1[e] = (PR - PL) + (XR + XL);
-        b0[e] = __builtin_fma((T)4, My[e], sY);
+        b0[e] = fma_t((T)4, My[e], sY);
         b1[e] = YR - YL;
         b2[e] = sY;
       }
@@ -287,17 +287,17 @@ __global__ __launch_bounds__(256) void adjoint_d2q9_fast(const typename C::elem*
         const T pa0 = a0[e] + b0[e], pa1 = a1[e] + b1[e], pa2 = a2[e] + b2[e];
         const T S2yy = (m0[e] + pa0) * k36;
         const T S1y = (pa0 - m0[e]) * k36;
-        const T S0 = __builtin_fma((T)4, c0[e], m0[e] + pa0) * k36;
+        const T S0 = fma_t((T)4, c0[e], m0[e] + pa0) * k36;
         const T S2xy = (pa1 - m1[e]) * k36;
-        const T S1x = __builtin_fma((T)4, c1[e], m1[e] + pa1) * k36;
-        const T S2xx = __builtin_fma((T)4, c2[e], m2[e] + pa2) * k36;
+        const T S1x = fma_t((T)4, c1[e], m1[e] + pa1) * k36;
+        const T S2xx = fma_t((T)4, c2[e], m2[e] + pa2) * k36;
         const T u = vx[e], v = vy[e];
-        const T uu = __builtin_fma(u, u, v * v);
-        const T su = __builtin_fma(S2xx, u, S2xy * v), sv = __builtin_fma(S2xy, u, S2yy * v);
-        const T quad = __builtin_fma(u, su, v * sv);
-        const T R = __builtin_fma(S0, __builtin_fma((T)1.5, uu, (T)1), (T)-4.5 * quad);
-        const T X = __builtin_fma((T)3, S1x, __builtin_fma((T)9, su, (T)-3 * u * S0));
-        const T Y = __builtin_fma((T)3, S1y, __builtin_fma((T)9, sv, (T)-3 * v * S0));
+        const T uu = fma_t(u, u, v * v);
+        const T su = fma_t(S2xx, u, S2xy * v), sv = fma_t(S2xy, u, S2yy * v);
+        const T quad = fma_t(u, su, v * sv);
+        const T R = fma_t(S0, fma_t((T)1.5, uu, (T)1), (T)-4.5 * quad);
+        const T X = fma_t((T)3, S1x, fma_t((T)9, su, (T)-3 * u * S0));
+        const T Y = fma_t((T)3, S1y, fma_t((T)9, sv, (T)-3 * v * S0));
         const int x = xb + e;
         const bool fixed = row_fixed || (!p.xper && (x == 0 || x == p.nx - 1));
         oR.v[e] = fixed ? (T)0 : R;

@@ -346,6 +346,17 @@ struct RawRow {
   RowVec<C, KX> f[4];
 };
 
+// c ? a : b on the bit patterns. A plain conditional between two elements of
+// one row is turned by the compiler into a load at a selected index, which
+// puts 16-bit rows in scratch memory.
+template <class E>
+__device__ __forceinline__ E pick_bits(bool c, E a, E b) {
+  using U = std::conditional_t<sizeof(E) == 2, uint16_t, std::conditional_t<sizeof(E) == 4, uint32_t, uint64_t>>;
+  static_assert(sizeof(U) == sizeof(E), "element size");
+  const U m = (U)0 - (U)c;
+  return __builtin_bit_cast(E, (U)((__builtin_bit_cast(U, a) & m) | (__builtin_bit_cast(U, b) & (U)~m)));
+}
+
 // PF: source planes loaded ahead (1 or 2).
 //
 // Memory goes through buffer resources of the four field planes, and every
@@ -366,13 +377,23 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
   constexpr int NX = 64 * KX;
   constexpr int ROWS = W + 2;
   constexpr int EB = (int)sizeof(E);
-  __shared__ float lds[2 * ROWS * 4 * NX];
+  // LDS slots of 4 x NX words: ROWS-1 upward slots (rows 0..ROWS-2 send to
+  // the next row) and ROWS-1 downward slots (rows 1..ROWS-1 send to the
+  // previous row). With two such sets (when they fit in the 160 KB of LDS),
+  // source planes alternate between them and one barrier per plane suffices:
+  // a set is written again only two planes later, after every wavefront has
+  // passed the barrier that follows its reads of that set.
+  constexpr int SLOTS = 2 * (ROWS - 1) * 4 * NX;
+  constexpr bool DB = 2 * SLOTS * 4 <= 160 * 1024;
+  __shared__ float lds[(DB ? 2 : 1) * SLOTS];
   const int lane = threadIdx.x;
   const int wv = threadIdx.y;
-  float* up = lds + wv * 4 * NX;               // what this wave's row sends to the next row
-  float* dn = lds + (ROWS + wv) * 4 * NX;      // ... and to the previous row
-  const float* from_below = lds + (wv > 0 ? wv - 1 : 0) * 4 * NX;
-  const float* from_above = lds + (ROWS + (wv + 1 < ROWS ? wv + 1 : wv)) * 4 * NX;
+  const int s_up = wv < ROWS - 1 ? wv : ROWS - 2;  // slot this row sends up to (unused by the top row)
+  const int s_dn = wv > 0 ? wv - 1 : 0;            // ... and down to (unused by the bottom row)
+  float* const up0 = lds + s_up * 4 * NX;
+  float* const dn0 = lds + (ROWS - 1 + s_dn) * 4 * NX;
+  const float* const below0 = lds + s_dn * 4 * NX;             // sent up by row wv-1
+  const float* const above0 = lds + (ROWS - 1 + s_up) * 4 * NX;  // sent down by row wv+1
 
   // XCD-aware tile numbering: XCD k (= blockIdx.x mod 8) gets a contiguous band
   const int bid = blockIdx.x;
@@ -421,8 +442,11 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
   // out of range. am / ac / ap are the accumulators of destination planes
   // zs-1, zs, zs+1; b holds plane zs and is refilled with plane zs+PF.
   auto source_plane = [&](auto store_c, int zs, PlaneAcc<KX>& am, PlaneAcc<KX>& ac, PlaneAcc<KX>& ap,
-                          RawRow<C, KX>& b) {
+                          RawRow<C, KX>& b, int set) {
     constexpr bool STORE = decltype(store_c)::value;
+    const int so = DB ? set * SLOTS : 0;
+    float* const up = up0 + so;
+    float* const dn = dn0 + so;
     float dr[KX], ux[KX], uy[KX], uz[KX];
 #pragma unroll
     for (int e = 0; e < KX; ++e) {
@@ -434,7 +458,7 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
       wprev[f] = wcur[f];
-      wcur[f] = lane == 0 ? b.f[f].v[0] : b.f[f].v[KX - 1];
+      wcur[f] = pick_bits(lane == 0, b.f[f].v[0], b.f[f].v[KX - 1]);
     }
     if (mode == 0)
       push_row<KX, 0>(dr, ux, uy, uz, p.rho_ref, am, ac, ap, up, dn, lane);
@@ -444,8 +468,8 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
       push_row<KX, 2>(dr, ux, uy, uz, p.rho_ref, am, ac, ap, up, dn, lane);
     load_plane(zs + PF, zs + PF <= z1, b);
     __syncthreads();
-    if (out_row) pull_rows<KX>(from_below, from_above, am, ac, ap, lane);
-    __syncthreads();
+    if (out_row) pull_rows<KX>(below0 + so, above0 + so, am, ac, ap, lane);
+    if constexpr (!DB) __syncthreads();
     const int zd = zs - 1;
     V o[4] = {};
     if (STORE && out_row) {
@@ -499,20 +523,20 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
   RawRow<C, KX>& c1 = PF == 2 ? b1 : b0;
 #pragma unroll
   for (int f = 0; f < 4; ++f) wcur[f] = E{};
-  source_plane(NoStore{}, z0 - 1, a0, a1, a2, b0);
-  source_plane(NoStore{}, z0, a1, a2, a0, c1);
+  source_plane(NoStore{}, z0 - 1, a0, a1, a2, b0, 0);
+  source_plane(NoStore{}, z0, a1, a2, a0, c1, 1);
   for (int zs = z0 + 1; zs <= z1; zs += 6) {
-    source_plane(Store{}, zs, a2, a0, a1, b0);
+    source_plane(Store{}, zs, a2, a0, a1, b0, 0);
     if (zs + 1 > z1) break;
-    source_plane(Store{}, zs + 1, a0, a1, a2, c1);
+    source_plane(Store{}, zs + 1, a0, a1, a2, c1, 1);
     if (zs + 2 > z1) break;
-    source_plane(Store{}, zs + 2, a1, a2, a0, b0);
+    source_plane(Store{}, zs + 2, a1, a2, a0, b0, 0);
     if (zs + 3 > z1) break;
-    source_plane(Store{}, zs + 3, a2, a0, a1, c1);
+    source_plane(Store{}, zs + 3, a2, a0, a1, c1, 1);
     if (zs + 4 > z1) break;
-    source_plane(Store{}, zs + 4, a0, a1, a2, b0);
+    source_plane(Store{}, zs + 4, a0, a1, a2, b0, 0);
     if (zs + 5 > z1) break;
-    source_plane(Store{}, zs + 5, a1, a2, a0, c1);
+    source_plane(Store{}, zs + 5, a1, a2, a0, c1, 1);
   }
 }
 
