@@ -59,8 +59,11 @@ struct CodecF64 {
   using elem = double;
   using T = double;
   static constexpr int bytes = 8;
+  static constexpr T kScaleRho = 1, kScaleU = 1;
   __device__ static T dec(elem s, int) { return s; }
+  __device__ static T dec_scaled(elem s, int) { return s; }
   __device__ static elem enc(T v, int, uint32_t) { return v; }
+  __device__ static elem enc_scaled(T v, int, uint32_t) { return v; }
   __device__ static elem enc_nearest(T v, int field) { return enc(v, field, 0u); }
 };
 
@@ -68,8 +71,11 @@ struct CodecF32 {
   using elem = float;
   using T = float;
   static constexpr int bytes = 4;
+  static constexpr T kScaleRho = 1, kScaleU = 1;
   __device__ static T dec(elem s, int) { return s; }
+  __device__ static T dec_scaled(elem s, int) { return s; }
   __device__ static elem enc(T v, int, uint32_t) { return v; }
+  __device__ static elem enc_scaled(T v, int, uint32_t) { return v; }
   __device__ static elem enc_nearest(T v, int field) { return enc(v, field, 0u); }
 };
 
@@ -79,14 +85,17 @@ struct CodecHILO {
   using elem = uint32_t;
   using T = float;
   static constexpr int bytes = 4;
+  static constexpr T kScaleRho = 1, kScaleU = 1;
   __device__ static T dec(elem s, int) {
     return bits_f32(s & 0xffff0000u) + bits_f32(s << 16);
   }
+  __device__ static T dec_scaled(elem s, int field) { return dec(s, field); }
   __device__ static elem enc(T v, int, uint32_t) {
     const __bf16 hi = (__bf16)v;
     const __bf16 lo = (__bf16)(v - (float)hi);
     return ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16) | (uint32_t)__builtin_bit_cast(uint16_t, lo);
   }
+  __device__ static elem enc_scaled(T v, int field, uint32_t bits) { return enc(v, field, bits); }
   __device__ static elem enc_nearest(T v, int field) { return enc(v, field, 0u); }
 };
 
@@ -99,22 +108,39 @@ struct CodecS16 {
   using elem = uint16_t;
   using T = float;
   static constexpr int bytes = 2;
-  __device__ static float scale(int field) { return field == 0 ? 1024.0f : 64.0f; }
-  __device__ static float inv_scale(int field) { return field == 0 ? (1.0f / 1024.0f) : (1.0f / 64.0f); }
+  static constexpr T kScaleRho = 1024.0f, kScaleU = 64.0f;
+  __device__ static float scale(int field) { return field == 0 ? kScaleRho : kScaleU; }
+  __device__ static float inv_scale(int field) { return field == 0 ? (1.0f / kScaleRho) : (1.0f / kScaleU); }
   __device__ static T dec(elem s, int field) {
     _Float16 h = __builtin_bit_cast(_Float16, s);
     return (float)h * inv_scale(field);
   }
-  // Stochastic rounding by the hardware conversion (v_cvt_sr_f16_f32, which
-  // rounds up with probability equal to the discarded fraction, drawn from
-  // the high bits of its random operand); field f uses the node's 32 random
-  // bits rotated by 8 f.
-  __device__ static elem enc(T v, int field, uint32_t node_bits) {
+  // the stored value itself: the field times scale(field)
+  __device__ static T dec_scaled(elem s, int) { return (float)__builtin_bit_cast(_Float16, s); }
+  // The rounding conversion (v_cvt_sr_f16_f32) rounds up with probability
+  // equal to the discarded fraction, drawn from the high bits of its random
+  // operand; field f uses the node's 32 random bits rotated by 8 f.
+  __device__ static uint32_t field_bits(uint32_t node_bits, int field) {
+    return field == 0 ? node_bits : ((node_bits << (8 * field)) | (node_bits >> (32 - 8 * field)));
+  }
+  // `vs` is the value already multiplied by scale(field).
+  __device__ static elem enc_scaled(T vs, int field, uint32_t node_bits) {
     typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-    const uint32_t r = field == 0 ? node_bits : ((node_bits << (8 * field)) | (node_bits >> (32 - 8 * field)));
     h2 h = {};
-    h = __builtin_amdgcn_cvt_sr_f16_f32(h, v * scale(field), r, false);
+    h = __builtin_amdgcn_cvt_sr_f16_f32(h, vs, field_bits(node_bits, field), false);
     return __builtin_bit_cast(uint16_t, h.x);
+  }
+  __device__ static elem enc(T v, int field, uint32_t node_bits) {
+    return enc_scaled(v * scale(field), field, node_bits);
+  }
+  // Two neighbouring scaled values of one field converted into the low and
+  // high halves of one 32-bit word (the same bits as two enc_scaled calls).
+  __device__ static uint32_t enc2_scaled(T a, T b, int field, uint32_t bits_a, uint32_t bits_b) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    h2 h = {};
+    h = __builtin_amdgcn_cvt_sr_f16_f32(h, a, field_bits(bits_a, field), false);
+    h = __builtin_amdgcn_cvt_sr_f16_f32(h, b, field_bits(bits_b, field), true);
+    return __builtin_bit_cast(uint32_t, h);
   }
   // Round to nearest (fields set from outside the time loop).
   __device__ static elem enc_nearest(T v, int field) {
@@ -175,6 +201,7 @@ __device__ __forceinline__ T div36(T x) {
   const T e = fma_t((T)-36, q, x);
   return fma_t(e, c, q);
 }
+
 
 // ------------------------------------------------------ cross-lane moves
 // DPP wave rotates: lane l receives the value of lane l-1 (lane 0 that of

@@ -43,21 +43,19 @@ struct alignas(sizeof(typename C::elem) * KX) RowVec {
   typename C::elem v[KX];
 };
 
+// Loads one row of one field as stored (times the codec's storage scale).
 template <class C, int KX>
 __device__ __forceinline__ void load_row(const typename C::elem* __restrict__ p, int field, float (&out)[KX]) {
   const RowVec<C, KX> r = *reinterpret_cast<const RowVec<C, KX>*>(p);
 #pragma unroll
-  for (int e = 0; e < KX; ++e) out[e] = (float)C::dec(r.v[e], field);
+  for (int e = 0; e < KX; ++e) out[e] = (float)C::dec_scaled(r.v[e], field);
 }
 
-// Stores one row of one field; with x walls the first node of lane 0 and the
-// last node of lane 63 (the wall nodes) are left untouched.
+// Stores one encoded row of one field; with x walls the first node of lane 0
+// and the last node of lane 63 (the wall nodes) are left untouched.
 template <class C, int KX>
-__device__ __forceinline__ void store_row(typename C::elem* __restrict__ p, int field, const float (&v)[KX],
-                                          const uint32_t (&bits)[KX], int lane, bool xwall) {
-  RowVec<C, KX> r;
-#pragma unroll
-  for (int e = 0; e < KX; ++e) r.v[e] = C::enc(v[e], field, bits[e]);
+__device__ __forceinline__ void store_row(typename C::elem* __restrict__ p, const RowVec<C, KX>& r, int lane,
+                                          bool xwall) {
   if (xwall && (lane == 0 || lane == 63)) {
 #pragma unroll
     for (int e = 0; e < KX; ++e) {
@@ -99,6 +97,46 @@ struct PlaneAcc {
   }
 };
 
+// Finalises the KX nodes of one row of destination plane accumulators a and
+// encodes them: drho' = r / 36 and u~' = (m + 36 g) / (36 rho_ref + r)
+// (Eqs. (4)-(5) with the sums carried times 36). The accumulators hold the
+// sums times K = the codec's density scale (a power of two; see node_links),
+// so K drho' = div36(a.r) and S u~' = S (a.m + 36 K g) / (36 K rho_ref + a.r)
+// for the velocity scale S: every scale is exact, and the stored values
+// carry them. The rounding bits of node e are hb ^ (e * 0x9e3779b9).
+template <class C, int KX>
+__device__ __forceinline__ void finalize_row(const PlaneAcc<KX>& a, float rho_ref, float g36x, float g36y, float g36z,
+                                             uint32_t hb, RowVec<C, KX> (&o)[4]) {
+#pragma clang fp contract(off)
+  constexpr float K = C::kScaleRho;
+  float v[4][KX];
+  uint32_t bits[KX];
+#pragma unroll
+  for (int e = 0; e < KX; ++e) {
+    const float inv = recip_f32(K * (36.f * rho_ref) + a.r[e]) * C::kScaleU;
+    v[0][e] = div36(a.r[e]);
+    v[1][e] = (a.mx[e] + K * g36x) * inv;
+    v[2][e] = (a.my[e] + K * g36y) * inv;
+    v[3][e] = (a.mz[e] + K * g36z) * inv;
+    bits[e] = hb ^ ((uint32_t)e * 0x9e3779b9u);
+  }
+  if constexpr (sizeof(typename C::elem) == 2 && KX % 2 == 0) {
+    struct Words { uint32_t w[KX / 2]; };
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      Words w;
+#pragma unroll
+      for (int e = 0; e < KX; e += 2) w.w[e / 2] = C::enc2_scaled(v[f][e], v[f][e + 1], f, bits[e], bits[e + 1]);
+      o[f] = __builtin_bit_cast(RowVec<C, KX>, w);
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int e = 0; e < KX; ++e) o[f].v[e] = C::enc_scaled(v[f][e], f, bits[e]);
+  }
+}
+
 // The 19 link values of one node, times 36, in deviation form (Eq. (2)):
 //   36 F^_a = wnum_a [a + c.b + sum_i c_i^2 q_ii + sum_{i<j} c_i c_j q_ij]
 // with a = drho - 1.5 rho |u|^2, b = 3 rho u, q_ii = 4.5 rho u_i^2,
@@ -113,15 +151,25 @@ struct Links {
 // Contraction is off and every FMA is written out, so a link value has the
 // same bits whichever wavefront (output or halo row) computes it and the
 // result does not depend on the tiling.
+//
+// The inputs are the stored fields times the codec's storage scales, d =
+// K drho and v = S u~ (K, S powers of two; 1 for FP32 storage), and every
+// link value comes out times K: with r3 = (3 K / S) rho each b and each
+// product c_ij = b_i v_j carries K resp. K S, and the constants that multiply
+// the c_ij are divided by S. Powers of two commute with every rounding, so
+// the scaled links are K times the unscaled ones, bit for bit.
+template <class C>
 __device__ __forceinline__ void node_links(float dr, float ux, float uy, float uz, float rho_ref, Links& L) {
 #pragma clang fp contract(off)
-  const float rho = rho_ref + dr;
-  const float r3 = 3.f * rho;
-  const float bx = r3 * ux, by = r3 * uy, bz = r3 * uz;    // 3 rho u
-  const float cxx = bx * ux, cyy = by * uy, czz = bz * uz;  // 3 rho u_i^2  (q_ii = 1.5 c_ii)
-  const float cxy = bx * uy, cxz = bx * uz, cyz = by * uz;  // 3 rho u_i u_j (q_ij = 3 c_ij)
-  const float a = __builtin_fmaf((cxx + cyy) + czz, -0.5f, dr);
-  const float sx = __builtin_fmaf(cxx, 1.5f, a), sy = __builtin_fmaf(cyy, 1.5f, a), sz = __builtin_fmaf(czz, 1.5f, a);
+  constexpr float K = C::kScaleRho, S = C::kScaleU;
+  const float rho = K == 1.f ? rho_ref + dr : __builtin_fmaf(dr, 1.f / K, rho_ref);
+  const float r3 = (3.f * K / S) * rho;
+  const float bx = r3 * ux, by = r3 * uy, bz = r3 * uz;    // 3 rho u          (times K)
+  const float cxx = bx * ux, cyy = by * uy, czz = bz * uz;  // 3 rho u_i^2      (times K S; q_ii = 1.5 c_ii)
+  const float cxy = bx * uy, cxz = bx * uz, cyz = by * uz;  // 3 rho u_i u_j    (times K S; q_ij = 3 c_ij)
+  const float a = __builtin_fmaf((cxx + cyy) + czz, -0.5f / S, dr);
+  const float sx = __builtin_fmaf(cxx, 1.5f / S, a), sy = __builtin_fmaf(cyy, 1.5f / S, a),
+              sz = __builtin_fmaf(czz, 1.5f / S, a);
   L.f0 = 12.f * a;
   L.hxp = sx + bx;
   L.hxm = sx - bx;
@@ -130,27 +178,27 @@ __device__ __forceinline__ void node_links(float dr, float ux, float uy, float u
   L.hzp = sz + bz;
   L.hzm = sz - bz;
   float t, p, m, u, v;
-  t = __builtin_fmaf(cyy, 1.5f, sx);  // a + q_xx + q_yy
-  p = __builtin_fmaf(cxy, 3.f, t);
-  m = __builtin_fmaf(cxy, -3.f, t);
+  t = __builtin_fmaf(cyy, 1.5f / S, sx);  // a + q_xx + q_yy
+  p = __builtin_fmaf(cxy, 3.f / S, t);
+  m = __builtin_fmaf(cxy, -3.f / S, t);
   u = bx + by;
   v = bx - by;
   L.pp0 = p + u;
   L.mm0 = p - u;
   L.pm0 = m + v;
   L.mp0 = m - v;
-  t = __builtin_fmaf(czz, 1.5f, sx);  // a + q_xx + q_zz
-  p = __builtin_fmaf(cxz, 3.f, t);
-  m = __builtin_fmaf(cxz, -3.f, t);
+  t = __builtin_fmaf(czz, 1.5f / S, sx);  // a + q_xx + q_zz
+  p = __builtin_fmaf(cxz, 3.f / S, t);
+  m = __builtin_fmaf(cxz, -3.f / S, t);
   u = bx + bz;
   v = bx - bz;
   L.p0p = p + u;
   L.m0m = p - u;
   L.p0m = m + v;
   L.m0p = m - v;
-  t = __builtin_fmaf(czz, 1.5f, sy);  // a + q_yy + q_zz
-  p = __builtin_fmaf(cyz, 3.f, t);
-  m = __builtin_fmaf(cyz, -3.f, t);
+  t = __builtin_fmaf(czz, 1.5f / S, sy);  // a + q_yy + q_zz
+  p = __builtin_fmaf(cyz, 3.f / S, t);
+  m = __builtin_fmaf(cyz, -3.f / S, t);
   u = by + bz;
   v = by - bz;
   L.zpp = p + u;
@@ -171,7 +219,7 @@ __device__ __forceinline__ void own_row_links(const float (&f0)[KX], const float
                                               const float (&hxm)[KX], const float (&m0p)[KX], const float (&m0m)[KX],
                                               PlaneAcc<KX>& am, PlaneAcc<KX>& ac, PlaneAcc<KX>& ap);
 
-template <int KX, int MODE>
+template <class C, int KX, int MODE>
 __device__ __forceinline__ void push_row(const float (&dr)[KX], const float (&ux)[KX], const float (&uy)[KX],
                                          const float (&uz)[KX], float rho_ref, PlaneAcc<KX>& am,
                                          PlaneAcc<KX>& ac, PlaneAcc<KX>& ap, float* __restrict__ up,
@@ -188,7 +236,7 @@ __device__ __forceinline__ void push_row(const float (&dr)[KX], const float (&ux
 #pragma unroll
   for (int e = 0; e < KX; ++e) {
     Links L;
-    node_links(dr[e], ux[e], uy[e], uz[e], rho_ref, L);
+    node_links<C>(dr[e], ux[e], uy[e], uz[e], rho_ref, L);
     hyp[e] = L.hyp;
     pp0[e] = L.pp0;
     mp0[e] = L.mp0;
@@ -450,10 +498,10 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
     float dr[KX], ux[KX], uy[KX], uz[KX];
 #pragma unroll
     for (int e = 0; e < KX; ++e) {
-      dr[e] = (float)C::dec(b.f[0].v[e], 0);
-      ux[e] = (float)C::dec(b.f[1].v[e], 1);
-      uy[e] = (float)C::dec(b.f[2].v[e], 2);
-      uz[e] = (float)C::dec(b.f[3].v[e], 3);
+      dr[e] = (float)C::dec_scaled(b.f[0].v[e], 0);
+      ux[e] = (float)C::dec_scaled(b.f[1].v[e], 1);
+      uy[e] = (float)C::dec_scaled(b.f[2].v[e], 2);
+      uz[e] = (float)C::dec_scaled(b.f[3].v[e], 3);
     }
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
@@ -461,11 +509,11 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
       wcur[f] = pick_bits(lane == 0, b.f[f].v[0], b.f[f].v[KX - 1]);
     }
     if (mode == 0)
-      push_row<KX, 0>(dr, ux, uy, uz, p.rho_ref, am, ac, ap, up, dn, lane);
+      push_row<C, KX, 0>(dr, ux, uy, uz, p.rho_ref, am, ac, ap, up, dn, lane);
     else if (mode == 1)
-      push_row<KX, 1>(dr, ux, uy, uz, p.rho_ref, am, ac, ap, up, dn, lane);
+      push_row<C, KX, 1>(dr, ux, uy, uz, p.rho_ref, am, ac, ap, up, dn, lane);
     else if (mode == 2)
-      push_row<KX, 2>(dr, ux, uy, uz, p.rho_ref, am, ac, ap, up, dn, lane);
+      push_row<C, KX, 2>(dr, ux, uy, uz, p.rho_ref, am, ac, ap, up, dn, lane);
     load_plane(zs + PF, zs + PF <= z1, b);
     __syncthreads();
     if (out_row) pull_rows<KX>(below0 + so, above0 + so, am, ac, ap, lane);
@@ -477,20 +525,7 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
       // spread to its KX nodes by distinct odd constants
       uint32_t hb = 0;
       if constexpr (needs_rng<C>::value) hb = sr_node_bits(p.sr_key, nx * ((int64_t)yrow + (int64_t)p.ny * zwrap(zd)) + xbase);
-#pragma unroll
-      for (int e = 0; e < KX; ++e) {
-        // drho' = r / 36, u~' = (m + 36 g) / (36 rho_ref + r)
-        const float inv = recip_f32(36.f * p.rho_ref + am.r[e]);
-        const float r = div36(am.r[e]);
-        const float vx = (am.mx[e] + p.g36x) * inv;
-        const float vy = (am.my[e] + p.g36y) * inv;
-        const float vz = (am.mz[e] + p.g36z) * inv;
-        const uint32_t bits = hb ^ ((uint32_t)e * 0x9e3779b9u);
-        o[0].v[e] = C::enc(r, 0, bits);
-        o[1].v[e] = C::enc(vx, 1, bits);
-        o[2].v[e] = C::enc(vy, 2, bits);
-        o[3].v[e] = C::enc(vz, 3, bits);
-      }
+      finalize_row<C, KX>(am, p.rho_ref, p.g36x, p.g36y, p.g36z, hb, o);
       if (wall_lane) {
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
@@ -547,7 +582,7 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
 // c_y = 0 links of its own row and, of the neighbouring rows, only the links
 // that reach it. Link values and the order of every sum are those of the
 // exchange kernel above, so both kernels give the same bits.
-template <int KX, int S>
+template <class C, int KX, int S>
 __device__ __forceinline__ void neighbour_row(const RowData<KX>& b, float rho_ref, int d_unused, PlaneAcc<KX>& am,
                                               PlaneAcc<KX>& ac, PlaneAcc<KX>& ap) {
   (void)d_unused;
@@ -555,7 +590,7 @@ __device__ __forceinline__ void neighbour_row(const RowData<KX>& b, float rho_re
 #pragma unroll
   for (int e = 0; e < KX; ++e) {
     Links L;
-    node_links(b.dr[e], b.ux[e], b.uy[e], b.uz[e], rho_ref, L);
+    node_links<C>(b.dr[e], b.ux[e], b.uy[e], b.uz[e], rho_ref, L);
     if constexpr (S > 0) {
       h[e] = L.hyp;
       ep[e] = L.pp0;
@@ -615,7 +650,7 @@ __global__ __launch_bounds__(64 * NWV) void step_d3q19_indep(const typename C::e
 #pragma unroll
       for (int e = 0; e < KX; ++e) {
         Links L;
-        node_links(own.dr[e], own.ux[e], own.uy[e], own.uz[e], p.rho_ref, L);
+        node_links<C>(own.dr[e], own.ux[e], own.uy[e], own.uz[e], p.rho_ref, L);
         f0[e] = L.f0;
         hzp[e] = L.hzp;
         hzm[e] = L.hzm;
@@ -629,31 +664,18 @@ __global__ __launch_bounds__(64 * NWV) void step_d3q19_indep(const typename C::e
       if (zs < z1) load(y, zs + 1, own);
       own_row_links<KX>(f0, hzp, hzm, hxp, p0p, p0m, hxm, m0p, m0m, am, ac, ap);
     }
-    neighbour_row<KX, 1>(below, p.rho_ref, 0, am, ac, ap);
+    neighbour_row<C, KX, 1>(below, p.rho_ref, 0, am, ac, ap);
     if (zs < z1) load(yb, zs + 1, below);
-    neighbour_row<KX, -1>(above, p.rho_ref, 0, am, ac, ap);
+    neighbour_row<C, KX, -1>(above, p.rho_ref, 0, am, ac, ap);
     if (zs < z1) load(ya, zs + 1, above);
     const int zd = zs - 1;
     if (zd >= z0) {
-      float r[KX], vx[KX], vy[KX], vz[KX];
-#pragma unroll
-      for (int e = 0; e < KX; ++e) {
-        // drho' = r / 36, u~' = (m + 36 g) / (36 rho_ref + r)
-        const float inv = recip_f32(36.f * p.rho_ref + am.r[e]);
-        r[e] = div36(am.r[e]);
-        vx[e] = (am.mx[e] + p.g36x) * inv;
-        vy[e] = (am.my[e] + p.g36y) * inv;
-        vz[e] = (am.mz[e] + p.g36z) * inv;
-      }
       const int64_t node0 = nx * ((int64_t)y + (int64_t)p.ny * zwrap(zd)) + xbase;
-      uint32_t bits[KX];
-      const uint32_t hb = needs_rng<C>::value ? sr_node_bits(p.sr_key, node0) : 0u;
+      const uint32_t hb = needs_rng<C>::value ? sr_node_bits(p.sr_key, node0) : 0u;  // as the exchange kernel
+      RowVec<C, KX> o[4];
+      finalize_row<C, KX>(am, p.rho_ref, p.g36x, p.g36y, p.g36z, hb, o);
 #pragma unroll
-      for (int e = 0; e < KX; ++e) bits[e] = hb ^ ((uint32_t)e * 0x9e3779b9u);  // as the exchange kernel
-      store_row<C, KX>(dst + node0, 0, r, bits, lane, p.xwall);
-      store_row<C, KX>(dst + plane + node0, 1, vx, bits, lane, p.xwall);
-      store_row<C, KX>(dst + 2 * plane + node0, 2, vy, bits, lane, p.xwall);
-      store_row<C, KX>(dst + 3 * plane + node0, 3, vz, bits, lane, p.xwall);
+      for (int f = 0; f < 4; ++f) store_row<C, KX>(dst + f * plane + node0, o[f], lane, p.xwall);
     }
   };
 
