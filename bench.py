@@ -59,7 +59,7 @@ def updated_nodes(case) -> int:
     return n
 
 
-def time_variant(case, precision, steps, warmup, autotune=True, tiling=None):
+def time_variant(case, precision, steps, warmup, autotune=True, tiling=None, copy=False):
     import torch
 
     from paper_1901_02716_amd import Simulation
@@ -86,8 +86,34 @@ def time_variant(case, precision, steps, warmup, autotune=True, tiling=None):
     ms = start.elapsed_time(stop)
     d = sim.diagnostics()
     d = {"diag": d, "tiling": sim.tiling_used}
+    if copy:
+        d["copy_ms"], d["copy_bytes"] = copy_rate(sim, steps, warmup)
     sim.close()
     return ms / steps, wall, d
+
+
+def copy_rate(sim, steps: int, warmup: int):
+    """The library's streaming copy of a state buffer back and forth between
+    two buffers of the step's size, as many times as the step was timed: the
+    memory rate of a step without its arithmetic. Returns ms per copy and the
+    bytes each copy moves (read + write)."""
+    import torch
+
+    nb = sim.state_bytes()
+    a = torch.zeros(nb, dtype=torch.uint8, device=sim.device)
+    b = torch.zeros_like(a)
+    sim.save_state(a)
+    for i in range(max(warmup, 2)):
+        sim.copy(a, b) if i % 2 == 0 else sim.copy(b, a)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(sim.stream)
+    for i in range(steps):
+        sim.copy(a, b) if i % 2 == 0 else sim.copy(b, a)
+    stop.record(sim.stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps, 2 * nb
 
 
 def time_adjoint(T: int, precision: str = "fp32", reps: int = 3):
@@ -269,11 +295,13 @@ def main(argv=None):
     if args.tiling:
         parts = args.tiling.split(",")
         tiling = tuple(int(v) for v in parts[:4]) + ((parts[4],) if len(parts) > 4 else ())
-    ms, wall, info = time_variant(case, args.precision, args.steps, args.warmup, not args.no_autotune, tiling)
+    ms, wall, info = time_variant(case, args.precision, args.steps, args.warmup, not args.no_autotune, tiling,
+                                  copy=True)
     diag = info["diag"]
     mlups = lu / (ms * 1e-3) / 1e6
     b_lu = 2 * (d + 1) * BYTES[args.precision]
     achieved = b_lu * lu / (ms * 1e-3) / 1e9
+    copy_gbs = info["copy_bytes"] / (info["copy_ms"] * 1e-3) / 1e9
     traffic = load_traffic(args.workload, args.precision)
 
     variants = {}
@@ -319,6 +347,11 @@ def main(argv=None):
                    "bytes_per_lattice_update": b_lu, "tiling": info["tiling"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+        "copy_ceiling": {"kernel": "maclab_copy: the state buffer copied back and forth (16-byte loads, "
+                                   "non-temporal 16-byte stores)",
+                         "bytes_per_copy": info["copy_bytes"], "ms_per_copy": round(info["copy_ms"], 5),
+                         "gbs": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),
+                         "step_frac_of_copy": round(achieved / copy_gbs, 4)},
         "cpu_baseline": cpu,
         "variants": variants,
         "adjoint": adjoint,

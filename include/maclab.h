@@ -138,7 +138,9 @@ int maclab_diagnostics(maclab_t h, double out[7]);
 int maclab_params(maclab_t h, double out[6]);
 
 /* Native state: the d+1 stored planes of the current step in storage format,
- * maclab_state_bytes(h) bytes. save copies it to caller device memory; load
+ * maclab_state_bytes(h) bytes. A plane holds the N nodes followed by padding
+ * (a plane stride of N rounded up to 512, plus 256 elements); the library
+ * never reads the padding, and keeps it zero in its own buffers. save copies it to caller device memory; load
  * restores it bitwise into both ping-pong buffers (including 16-bit
  * storage), so a run resumed from a saved state repeats the original bit for
  * bit (for S16 the rounding stream is keyed by the step counter, which load
@@ -180,7 +182,8 @@ int maclab_autotune(maclab_t h, int reps, double* best_ms);
 int maclab_set_body_force(maclab_t h, const double* G);
 
 /* One step from the native state at src to dst (both caller-owned device
- * buffers of maclab_state_bytes; dst receives the fixed-face values too),
+ * buffers of maclab_state_bytes; dst receives the fixed-face values too, and
+ * its plane padding is left as it was),
  * with the rounding stream of step `step_index`. The handle's own state and
  * step counter are untouched. Used to recompute a trajectory segment from a
  * checkpoint. */
@@ -283,6 +286,15 @@ int maclab_batch_set_graph(maclab_batch_t b, int steps_per_graph);
 int maclab_batch_autotune(maclab_batch_t b, int reps, double* best_ms);
 void maclab_batch_destroy(maclab_batch_t b);
 const char* maclab_batch_last_error(maclab_batch_t b);
+
+/* Calibration: copies `bytes` from src to dst (caller device memory, 16-byte
+ * aligned, not overlapping; bytes a multiple of 16) on the handle's stream
+ * with 16-byte loads and the non-temporal 16-byte stores of the step
+ * kernels. Copying a state buffer back and forth moves the bytes of a step
+ * without its arithmetic, which gives the memory rate a step can reach on
+ * the device. Asynchronous. MACLAB_EINVAL for a NULL or misaligned pointer
+ * or a size that is not a multiple of 16. */
+int maclab_copy(maclab_t h, const void* src, void* dst, size_t bytes);
 
 /* Releases the handle (not the caller's memory). NULL is ignored. */
 void maclab_destroy(maclab_t h);

@@ -23,7 +23,7 @@ struct FaceValues {
 struct Layout {
   int q = 0, d = 0, precision = 0, bytes = 0;
   int64_t nx = 0, ny = 0, nz = 0, N = 0;
-  int64_t plane = 0;          // elements per plane (N rounded up)
+  int64_t plane = 0;          // elements between field planes (N rounded up, plus 256)
   size_t state_bytes = 0;     // (d + 1) planes
   size_t partial_bytes = 0;   // reduction partials
   size_t staging_bytes = 0;   // host transfer staging
@@ -44,6 +44,8 @@ hipError_t launch_encode(const Layout& L, void* plane_dst, const double* src, in
                          double mul, int field, hipStream_t s);
 hipError_t launch_decode(const Layout& L, double* dst, const void* plane_src, int64_t count, double offset,
                          double mul, int field, hipStream_t s);
+// Streaming copy of `bytes` (a multiple of 16; 16-byte aligned, disjoint).
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_diagnostics(const Layout& L, const void* state, double rho_ref, double e, double* partials,
                               double* result, hipStream_t s);
 

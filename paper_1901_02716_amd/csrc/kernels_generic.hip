@@ -282,4 +282,24 @@ hipError_t launch_diagnostics(const Layout& L, const void* state, double rho_ref
   return hipGetLastError();
 }
 
+// Streaming copy of n16 16-byte words: 16-byte loads and non-temporal 16-byte
+// stores, the store form of the step kernels. It moves the bytes of a step
+// with none of its arithmetic, so its rate is the memory rate a step can
+// reach.
+__global__ void stream_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16) {
+  typedef uint32_t w4 __attribute__((ext_vector_type(4)));
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    __builtin_nontemporal_store(__builtin_bit_cast(w4, src[i]), reinterpret_cast<w4*>(dst + i));
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 == 0) return hipSuccess;
+  const int64_t want = (n16 + 255) / 256;
+  const unsigned blocks = (unsigned)(want < 8192 ? want : 8192);
+  hipLaunchKernelGGL(stream_copy_kernel, dim3(blocks), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, n16);
+  return hipGetLastError();
+}
+
 }  // namespace maclab

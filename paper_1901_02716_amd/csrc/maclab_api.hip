@@ -126,7 +126,10 @@ int make_layout(const maclab_config* c, Layout* L, std::string* why) {
   L->ny = c->n[1];
   L->nz = c->n[2];
   L->N = N;
-  L->plane = (int64_t)round_up((size_t)N, 512);
+  // 256 elements past a multiple of 512: the field planes of a power-of-two
+  // lattice then do not start at addresses that differ only in their high
+  // bits, which costs about 2% in a 256^3 step
+  L->plane = (int64_t)round_up((size_t)N, 512) + 256;
   L->state_bytes = (size_t)(d + 1) * (size_t)L->plane * (size_t)L->bytes;
   L->partial_bytes = round_up(sizeof(double) * (kDiagBlocks + 1) * kDiagValues, kAlign);
   L->staging_bytes = std::min(kStagingMax, round_up(sizeof(double) * (size_t)N, kAlign));
@@ -566,6 +569,17 @@ int maclab_step_external(maclab_t h, const void* src, void* dst, int64_t step_in
   bool any_fixed = false;
   for (int f = 0; f < 6; ++f) any_fixed |= h->fv.kind[f] == MACLAB_BC_FIXED;
   if (any_fixed) HIP_TRY(h, launch_impose_bc(h->L, dst, dst, h->fv, h->cfg.rho_ref, h->e, h->stream));
+  return MACLAB_OK;
+}
+
+int maclab_copy(maclab_t h, const void* src, void* dst, size_t bytes) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!src || !dst) return fail(h, MACLAB_EINVAL, "src and dst must be device pointers");
+  if (((uintptr_t)src | (uintptr_t)dst | bytes) & 15)
+    return fail(h, MACLAB_EINVAL, "src, dst and bytes must be multiples of 16");
+  const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+  if (a < b + bytes && b < a + bytes) return fail(h, MACLAB_EINVAL, "src and dst overlap");
+  HIP_TRY(h, launch_stream_copy(src, dst, bytes, h->stream));
   return MACLAB_OK;
 }
 

@@ -162,6 +162,13 @@ class Simulation:
         state_bytes()); the simulation's own state does not change."""
         _lib.check(self.lib.maclab_step_external(self.h, src.data_ptr(), dst.data_ptr(), int(step_index)), self.h)
 
+    def copy(self, src: torch.Tensor, dst: torch.Tensor, nbytes: int | None = None) -> None:
+        """Streaming device copy on the simulation's stream (calibration: the
+        memory rate of a step without its arithmetic)."""
+        n = src.numel() * src.element_size() if nbytes is None else int(nbytes)
+        assert n <= src.numel() * src.element_size() and n <= dst.numel() * dst.element_size()
+        _lib.check(self.lib.maclab_copy(self.h, src.data_ptr(), dst.data_ptr(), n), self.h)
+
     def adjoint_bytes(self) -> int:
         return int(self.lib.maclab_adjoint_bytes(self.h))
 

@@ -439,3 +439,23 @@ def test_fast2d_is_the_default_for_cavities():
     assert sim.tiling()["kernel"] == "fast2d"
     gen = make_sim(workloads.random_field(9, (37, 23, 1), seed=1), "fp32")  # periodic, ragged width
     assert gen.tiling()["kernel"] == "general"
+
+
+def test_copy_calibration_kernel():
+    """maclab_copy (the calibration copy bench.py times) copies bit for bit
+    and rejects misaligned, overlapping or odd-sized requests."""
+    case = _fast_case(64, (10, 9), ("x", "y", "z"), (0, 0, 0))
+    sim = make_sim(case, "fp32")
+    g = torch.Generator().manual_seed(5)
+    a = torch.randint(0, 256, (3 << 20,), dtype=torch.uint8, generator=g).to(sim.device)
+    b = torch.zeros_like(a)
+    sim.copy(a, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    c = torch.zeros_like(a)
+    sim.copy(a, c, 4096 + 16)
+    torch.cuda.synchronize()
+    assert torch.equal(c[:4112], a[:4112]) and not c[4112:].any()
+    for bad in ((a[1:], b, 16), (a, a[16:], 1024), (a, b, 17)):
+        with pytest.raises(MaclabError):
+            sim.copy(*bad)
