@@ -228,6 +228,29 @@ def time_batch(steps: int, sep_steps: int):
     return out
 
 
+def time_small(steps: int = 2000):
+    """The launch-bound case: the 64^2 periodic Taylor-Green vortex in FP64
+    (4096 nodes), one launch per step."""
+    import torch
+
+    from paper_1901_02716_amd import Simulation, workloads
+
+    case = workloads.taylor_green(n=64, nu=0.01, U0=0.01)
+    sim = Simulation(9, case.n, case.dx, case.nu, precision="fp64")
+    sim.set_fields(case.rho, case.u)
+    sim.step(100)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(sim.stream)
+    sim.step(steps)
+    b.record(sim.stream)
+    torch.cuda.synchronize()
+    us = a.elapsed_time(b) / steps * 1e3
+    sim.close()
+    return {"workload": "D2Q9 Taylor-Green vortex 64^2 FP64 (launch-bound)", "steps_timed": steps,
+            "us_per_step": round(us, 3), "mlups": round(case.n[0] * case.n[1] / us, 1)}
+
+
 def cpu_baseline(case, steps: int):
     """The FP64 oracle on `steps` steps of the same lattice, one thread."""
     import oracle
@@ -314,6 +337,7 @@ def main(argv=None):
 
     adjoint = time_adjoint(args.adjoint_steps) if args.adjoint_steps > 0 else None
     batch = time_batch(args.batch_steps, max(10, args.batch_steps // 4)) if args.batch_steps > 0 else None
+    small = time_small() if args.batch_steps > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -356,6 +380,7 @@ def main(argv=None):
         "variants": variants,
         "adjoint": adjoint,
         "batch": batch,
+        "launch_bound": small,
         "diagnostics_after": {"mass": diag[0], "max_u_over_e": diag[5], "nonfinite": diag[6]},
         "wall_s": round(wall, 3),
         "kernel_source_hash": kernel_source_hash(),
