@@ -98,8 +98,14 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src, typename C::elem* 
   constexpr int SW = 64 * KX;
   constexpr int EB = (int)sizeof(E);
   const int lane = threadIdx.x & 63;
-  // the work item is uniform across the wavefront: keep it in scalar registers
-  const int g = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  // XCD-aware numbering: workgroups go to the eight XCDs in turn (blockIdx.x
+  // mod 8), so XCD k is given a contiguous range of work items -- the bands
+  // of a lattice next to each other, whose boundary rows its L2 then shares.
+  // The work item is uniform across the wavefront: keep it in scalar registers.
+  const int nblk = (int)gridDim.x, bid = (int)blockIdx.x;
+  const int per = nblk >> 3, rem = nblk & 7, xcd = bid & 7;
+  const int lblk = xcd * per + (xcd < rem ? xcd : rem) + (bid >> 3);
+  const int g = __builtin_amdgcn_readfirstlane(lblk * 4 + (int)(threadIdx.x >> 6));
   if (g >= p.nitems) return;
   Lattice2D lt;
   int x0, y0, y1;

@@ -141,7 +141,13 @@ __global__ __launch_bounds__(256) void adjoint_d2q9_fast(const typename C::elem*
   using T = typename C::T;
   constexpr int SW = 64 * KX;
   const int lane = threadIdx.x & 63;
-  const int g = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  // XCD-aware numbering (workgroups go to the eight XCDs in turn): XCD k
+  // takes a contiguous range of (segment, band) items, so neighbouring bands
+  // share their boundary rows through its L2
+  const int nblk = (int)gridDim.x, bid = (int)blockIdx.x;
+  const int per = nblk >> 3, rem = nblk & 7, xcd = bid & 7;
+  const int lblk = xcd * per + (xcd < rem ? xcd : rem) + (bid >> 3);
+  const int g = __builtin_amdgcn_readfirstlane(lblk * 4 + (int)(threadIdx.x >> 6));
   if (g >= p.nitems) return;
   const int seg = g % p.nseg, band = g / p.nseg;
   const int x0 = seg * SW;
