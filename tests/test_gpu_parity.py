@@ -459,3 +459,24 @@ def test_copy_calibration_kernel():
     for bad in ((a[1:], b, 16), (a, a[16:], 1024), (a, b, 17)):
         with pytest.raises(MaclabError):
             sim.copy(*bad)
+
+
+def test_zero_steps_and_smallest_walled_lattices():
+    """step(0) changes nothing; walled lattices with a single interior node
+    per walled axis (3 x 3 D2Q9, 3 x 3 x 3 and 64 x 3 x 3 D3Q19, on the
+    general, fast D2Q9 and fast D3Q19 kernels) follow the oracle."""
+    for q, n, prec, tol in ((9, (3, 3, 1), "fp32", 1e-5), (19, (3, 3, 3), "fp64", 1e-12),
+                            (19, (64, 3, 3), "fp32", 1e-5)):
+        case = workloads.random_field(q, n, seed=12, amp=0.03)
+        for ax in ("xyz"[:case.d]):
+            case.fixed[ax + "lo"] = (1.0, (0.0, 0.0, 0.0))
+            case.fixed[ax + "hi"] = (1.002, (0.02, 0.0, 0.0))
+        sim = make_sim(case, prec)
+        s0 = sim.save_state().clone()
+        sim.step(0)
+        assert torch.equal(sim.save_state(), s0) and sim.params()["steps"] == 0
+        print(f"  {q} {n} {prec}: kernel {sim.tiling()['kernel']}", flush=True)
+        sim.step(9)
+        rho, u = sim.fields()
+        orho, ou = oracle.run(to_problem(case), case.rho, case.u, 9)
+        assert rel_l2(u, ou) < tol and rel_l2(rho, orho) < tol, (q, n, prec)
