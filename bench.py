@@ -16,10 +16,11 @@ and the FP64 CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -37,9 +38,16 @@ BYTES = {"fp64": 8, "fp32": 4, "hilo": 4, "s16": 2}
 
 
 def kernel_source_hash() -> str:
+    """sha256 (first 16 hex digits) of the library sources with comments and
+    blank lines removed, so that an edit of a comment keeps the counter
+    figures taken on the same code."""
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(ROOT, "paper_1901_02716_amd", "csrc", "*"))):
-        h.update(open(p, "rb").read())
+        text = open(p, encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 

@@ -16,7 +16,9 @@
 //        wavefront, which reads them at x, x-1 or x+1.
 //  - After source plane z is pushed, destination plane z-1 holds the full
 //    gathers of Eqs. (4)-(5) and is finalised: rho' = rho_ref + drho',
-//    u~' = (m' + g) / rho', and stored (fixed nodes are skipped).
+//    u~' = (m' + g) / rho', and stored: rows and planes of fixed faces are
+//    never written, and a fixed node at either end of a row is written back
+//    with its unchanged stored value.
 //  - Workgroups are numbered so that each XCD gets a contiguous band of tiles
 //    (neighbouring tiles share halo rows through that XCD's L2).
 #include "internal.h"
