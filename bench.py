@@ -7,9 +7,18 @@ updated (non-wall) nodes, 254^3 per step. The split-storage variants (S16 =
 scaled binary16 with stochastic rounding, HILO = bfloat16 hi+lo) are timed on
 the same lattice and reported beside it.
 
-Output: one JSON line (rank 0) with the metric, the roofline of the step
-kernel (algorithmic bytes per launch / measured launch time against 8 TB/s),
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+Output: one JSON line with
+  - the metric and `value` (MLUPS of the FP32 step, inputs resident in HBM);
+  - `roofline`: algorithmic bytes per launch / measured launch time against
+    8 TB/s, and the HBM bytes per launch from the committed rocprofv3
+    counters when they were taken on the current sources;
+  - `copy_ceiling`: the library's streaming copy of the same state buffer
+    back and forth, the memory rate a step can reach on this device;
+  - `cpu_baseline`: the FP64 CPU oracle timed on a bounded sample of the
+    same workload;
+  - `variants` (S16, HILO), `adjoint` (the 512^2 D2Q9 reverse mode against
+    the forward), `batch` (512 D2Q9 cavities in one launch per step against
+    one launch per cavity) and `launch_bound` (a 64^2 lattice).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """

@@ -52,7 +52,6 @@ struct StepParams {
 // --------------------------------------------------------- storage codecs
 // A codec maps the compute type T to the stored element and back. Field index
 // 0 is the density deviation rho - rho_ref, fields 1..D are u~.
-__device__ __forceinline__ uint32_t f32_bits(float v) { return __float_as_uint(v); }
 __device__ __forceinline__ float bits_f32(uint32_t b) { return __uint_as_float(b); }
 
 struct CodecF64 {

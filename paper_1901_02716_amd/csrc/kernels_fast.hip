@@ -81,15 +81,6 @@ __device__ __forceinline__ void store_row(typename C::elem* __restrict__ p, cons
   }
 }
 
-// Lane l receives the value of lane l-1 (lane 0 that of lane 63).
-__device__ __forceinline__ float from_left_lane(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x13C, 0xF, 0xF, false));
-}
-// Lane l receives the value of lane l+1 (lane 63 that of lane 0).
-__device__ __forceinline__ float from_right_lane(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xF, 0xF, false));
-}
-
 template <int KX>
 struct PlaneAcc {
   float r[KX], mx[KX], my[KX], mz[KX];  // 36 * (drho', m')
@@ -267,7 +258,7 @@ __device__ __forceinline__ void push_row(const float (&dr)[KX], const float (&ux
   // touches 64 consecutive words.
   auto send = [&](float* __restrict__ buf, const float (&h)[KX], const float (&ep)[KX], const float (&em)[KX],
                   const float (&vp)[KX], const float (&vm)[KX]) {
-    const float in_ep = from_left_lane(ep[KX - 1]), in_em = from_right_lane(em[0]);
+    const float in_ep = dpp_from_left(ep[KX - 1]), in_em = dpp_from_right(em[0]);
 #pragma unroll
     for (int e = 0; e < KX; ++e) {
       const float a = e > 0 ? ep[e - 1] : in_ep, b = e < KX - 1 ? em[e + 1] : in_em;
@@ -292,9 +283,9 @@ __device__ __forceinline__ void own_row_links(const float (&f0)[KX], const float
                                               const float (&hxm)[KX], const float (&m0p)[KX], const float (&m0m)[KX],
                                               PlaneAcc<KX>& am, PlaneAcc<KX>& ac, PlaneAcc<KX>& ap) {
 #pragma clang fp contract(off)
-  const float in_hxp = from_left_lane(hxp[KX - 1]), in_p0p = from_left_lane(p0p[KX - 1]),
-              in_p0m = from_left_lane(p0m[KX - 1]);
-  const float in_hxm = from_right_lane(hxm[0]), in_m0p = from_right_lane(m0p[0]), in_m0m = from_right_lane(m0m[0]);
+  const float in_hxp = dpp_from_left(hxp[KX - 1]), in_p0p = dpp_from_left(p0p[KX - 1]),
+              in_p0m = dpp_from_left(p0m[KX - 1]);
+  const float in_hxm = dpp_from_right(hxm[0]), in_m0p = dpp_from_right(m0p[0]), in_m0m = dpp_from_right(m0m[0]);
 #pragma unroll
   for (int d = 0; d < KX; ++d) {
     // links arriving at node d from d-1 (moving +x) and d+1 (moving -x)
@@ -607,8 +598,8 @@ __device__ __forceinline__ void neighbour_row(const RowData<KX>& b, float rho_re
       vm[e] = L.zmm;
     }
   }
-  const float in_ep = from_left_lane(ep[KX - 1]);
-  const float in_em = from_right_lane(em[0]);
+  const float in_ep = dpp_from_left(ep[KX - 1]);
+  const float in_em = dpp_from_right(em[0]);
 #pragma unroll
   for (int d = 0; d < KX; ++d) {
     const float epl = d > 0 ? ep[d - 1] : in_ep;
