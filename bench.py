@@ -18,7 +18,8 @@ Output: one JSON line with
     same workload;
   - `variants` (S16, HILO), `adjoint` (the 512^2 D2Q9 reverse mode against
     the forward), `batch` (512 D2Q9 cavities in one launch per step against
-    one launch per cavity) and `launch_bound` (a 64^2 lattice).
+    one launch per cavity), `launch_bound` (a 64^2 lattice) and
+    `steady_state` (the paper's 2-D cavity run to a steady state).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -271,6 +272,30 @@ def time_small(steps: int = 2000):
             "us_per_step": round(us, 3), "mlups": round(case.n[0] * case.n[1] / us, 1)}
 
 
+def time_steady(tol: float = 1e-10, check_every: int = 5000):
+    """The steady-state driver on the paper's 2-D cavity (400 x 400 lattices,
+    u0 = 1, Re = 1000), FP64: steps until the per-step change of u is below
+    `tol`, with the residual evaluated every `check_every` steps."""
+    import torch
+
+    from paper_1901_02716_amd import Simulation, workloads
+
+    case = workloads.cavity_2d(n=401, Re=1000.0, U=1.0)
+    sim = Simulation(9, case.n, case.dx, case.nu, precision="fp64")
+    sim.set_fields(case.rho, case.u)
+    for face, (rb, ub) in case.fixed.items():
+        sim.set_bc(face, rb, ub)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, r = sim.run_to_steady(tol, 2000000, check_every)
+    wall = time.perf_counter() - t0
+    lu = updated_nodes(case) * steps
+    sim.close()
+    return {"workload": "D2Q9 lid-driven cavity 401^2 (400 x 400 lattices), u0 = 1, Re = 1000, FP64",
+            "tol_per_step": tol, "check_every": check_every, "steps": steps, "residual": r,
+            "wall_s": round(wall, 3), "mlups": round(lu / wall / 1e6, 1)}
+
+
 def cpu_baseline(case, steps: int):
     """The FP64 oracle on `steps` steps of the same lattice, one thread."""
     import oracle
@@ -358,6 +383,7 @@ def main(argv=None):
     adjoint = time_adjoint(args.adjoint_steps) if args.adjoint_steps > 0 else None
     batch = time_batch(args.batch_steps, max(10, args.batch_steps // 4)) if args.batch_steps > 0 else None
     small = time_small() if args.batch_steps > 0 else None
+    steady = time_steady() if args.batch_steps > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -401,6 +427,7 @@ def main(argv=None):
         "adjoint": adjoint,
         "batch": batch,
         "launch_bound": small,
+        "steady_state": steady,
         "diagnostics_after": {"mass": diag[0], "max_u_over_e": diag[5], "nonfinite": diag[6]},
         "wall_s": round(wall, 3),
         "kernel_source_hash": kernel_source_hash(),

@@ -296,6 +296,24 @@ const char* maclab_batch_last_error(maclab_batch_t b);
  * or a size that is not a multiple of 16. */
 int maclab_copy(maclab_t h, const void* src, void* dst, size_t bytes);
 
+/* Steady state (recipe step (v): the computation is repeated until a
+ * solution is reached). maclab_residual gives the change over the last step
+ * from the two ping-pong buffers, which hold the last two states:
+ * out[0] = max over nodes and components of |u_i(n) - u_i(n-1)| (physical
+ * units), out[1] = max |rho(n) - rho(n-1)|, out[2] = the count of nodes of
+ * state n holding a non-finite value (not counted in out[0], out[1]). After
+ * init, set_fields or load_state, before any step, both buffers hold the same
+ * state and the change is 0. Synchronises.
+ * maclab_step_until steps in blocks of check_every steps and evaluates the
+ * residual after each block, until out[0] < tol or max_steps steps are done;
+ * *done (may be NULL) receives the steps taken and resid (may be NULL) the
+ * last residual. MACLAB_OK whether or not it converged (compare resid[0]
+ * with tol); MACLAB_ENONFINITE as soon as a check finds non-finite nodes;
+ * MACLAB_EINVAL for tol < 0, max_steps < 0 or check_every < 1. */
+int maclab_residual(maclab_t h, double out[3]);
+int maclab_step_until(maclab_t h, double tol, int64_t max_steps, int64_t check_every, int64_t* done,
+                      double resid[3]);
+
 /* Releases the handle (not the caller's memory). NULL is ignored. */
 void maclab_destroy(maclab_t h);
 

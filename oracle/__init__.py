@@ -18,6 +18,9 @@ Every function mirrors one step of the paper (Zhou, arXiv:1901.02716):
   non-finite count (the conserved moments of Methods, Eqs. (14)-(15)).
 * :func:`adjoint_run` -- reverse-mode derivative of :func:`run` for a
   squared-error loss on the final velocity.
+* :func:`residual` -- the change of the fields over one step, by which the
+  solution procedure (step (v) after Eq. (6)) is repeated until a solution
+  is reached.
 """
 from __future__ import annotations
 
@@ -246,3 +249,11 @@ def adjoint_run(p: Problem, rho0: np.ndarray, u0: np.ndarray, steps: int, u_targ
     if rc != 0:
         raise ValueError(f"oracle_adjoint_run failed ({rc})")
     return float(loss[0]), gu, gG
+
+
+def residual(rho_a: np.ndarray, u_a: np.ndarray, rho_b: np.ndarray, u_b: np.ndarray) -> tuple[float, float]:
+    """Change from state a to state b (consecutive steps of :func:`run`):
+    the largest |u_i(b) - u_i(a)| over nodes and components and the largest
+    |rho(b) - rho(a)|, physical units (solution procedure, step (v): repeat
+    until a solution is reached)."""
+    return float(np.max(np.abs(u_b - u_a))), float(np.max(np.abs(rho_b - rho_a)))

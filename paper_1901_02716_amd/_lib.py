@@ -24,7 +24,8 @@ SYMBOLS = (
     "maclab_get_adjoint_tiling", "maclab_batch_workspace_bytes", "maclab_batch_init", "maclab_batch_lattice",
     "maclab_batch_count", "maclab_batch_step", "maclab_batch_step_separate", "maclab_batch_get_tiling",
     "maclab_batch_set_tiling", "maclab_batch_set_graph", "maclab_batch_autotune", "maclab_batch_destroy",
-    "maclab_batch_last_error", "maclab_copy", "maclab_destroy", "maclab_last_error",
+    "maclab_batch_last_error", "maclab_residual", "maclab_step_until", "maclab_copy", "maclab_destroy",
+    "maclab_last_error",
 )
 
 
@@ -111,6 +112,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.maclab_batch_last_error.restype = ctypes.c_char_p
     lib.maclab_batch_last_error.argtypes = [H]
     lib.maclab_copy.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
+    lib.maclab_residual.argtypes = [H, dp]
+    lib.maclab_step_until.argtypes = [H, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_int64), dp]
     lib.maclab_destroy.restype = None
     lib.maclab_destroy.argtypes = [H]
     lib.maclab_last_error.restype = ctypes.c_char_p

@@ -44,6 +44,11 @@ hipError_t launch_encode(const Layout& L, void* plane_dst, const double* src, in
                          double mul, int field, hipStream_t s);
 hipError_t launch_decode(const Layout& L, double* dst, const void* plane_src, int64_t count, double offset,
                          double mul, int field, hipStream_t s);
+// Largest change of u~ and of drho from state `prev` to state `cur` and the
+// count of non-finite nodes in `cur`, into result[0..2] (FP64, in storage
+// units); partials holds kDiagBlocks x 4 doubles.
+hipError_t launch_residual(const Layout& L, const void* prev, const void* cur, double* partials, double* result,
+                           hipStream_t s);
 // Streaming copy of `bytes` (a multiple of 16; 16-byte aligned, disjoint).
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_diagnostics(const Layout& L, const void* state, double rho_ref, double e, double* partials,

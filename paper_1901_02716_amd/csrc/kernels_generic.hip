@@ -204,6 +204,73 @@ __global__ __launch_bounds__(256) void diag_final_kernel(const double* __restric
   }
 }
 
+// Change over the last step (recipe step (v): the run goes on until a
+// solution is reached): per block, the largest |u~_i(b) - u~_i(a)| over nodes
+// and components, the largest |drho(b) - drho(a)|, and the count of nodes
+// non-finite in b. Maxima do not depend on the order of the reduction.
+template <class C>
+__global__ __launch_bounds__(256) void residual_partial_kernel(const typename C::elem* __restrict__ a,
+                                                               const typename C::elem* __restrict__ b, int64_t N,
+                                                               int64_t plane, int d, double* __restrict__ partials) {
+  double du = 0, dr = 0, bad = 0;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const double rb = (double)C::dec(b[x], 0);
+    bool finite = isfinite(rb);
+    double m = 0;
+    for (int c = 1; c <= d; ++c) {
+      const double ub = (double)C::dec(b[c * plane + x], c);
+      finite = finite && isfinite(ub);
+      m = fmax(m, fabs(ub - (double)C::dec(a[c * plane + x], c)));
+    }
+    if (!finite) {
+      bad += 1.0;
+      continue;
+    }
+    du = fmax(du, m);
+    dr = fmax(dr, fabs(rb - (double)C::dec(a[x], 0)));
+  }
+  __shared__ double red[3][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  du = wave_max(du);
+  dr = wave_max(dr);
+  bad = wave_sum(bad);
+  if (lane == 0) {
+    red[0][wave] = du;
+    red[1][wave] = dr;
+    red[2][wave] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int v = threadIdx.x;
+    double r = red[v][0];
+    for (int w = 1; w < 4; ++w) r = v < 2 ? fmax(r, red[v][w]) : r + red[v][w];
+    partials[(int64_t)blockIdx.x * 4 + v] = r;
+  }
+}
+
+__global__ __launch_bounds__(256) void residual_final_kernel(const double* __restrict__ partials, int nblocks,
+                                                             double* __restrict__ out) {
+  __shared__ double red[3][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int v = 0; v < 3; ++v) {
+    double acc = 0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+      const double x = partials[(int64_t)b * 4 + v];
+      acc = v < 2 ? fmax(acc, x) : acc + x;
+    }
+    const double r = v < 2 ? wave_max(acc) : wave_sum(acc);
+    if (lane == 0) red[v][wave] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int v = threadIdx.x;
+    double r = red[v][0];
+    for (int w = 1; w < 4; ++w) r = v < 2 ? fmax(r, red[v][w]) : r + red[v][w];
+    out[v] = r;
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 template <class F>
 static hipError_t dispatch_codec(int precision, F&& f) {
@@ -291,6 +358,21 @@ __global__ void stream_copy_kernel(const uint4* __restrict__ src, uint4* __restr
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
     __builtin_nontemporal_store(__builtin_bit_cast(w4, src[i]), reinterpret_cast<w4*>(dst + i));
+}
+
+hipError_t launch_residual(const Layout& L, const void* prev, const void* cur, double* partials, double* result,
+                           hipStream_t s) {
+  const int64_t want = (L.N + 255) / 256;
+  const int blocks = (int)(want < kDiagBlocks ? (want > 0 ? want : 1) : kDiagBlocks);
+  hipError_t err = dispatch_codec(L.precision, [&](auto codec) {
+    using C = decltype(codec);
+    hipLaunchKernelGGL((residual_partial_kernel<C>), dim3(blocks), dim3(256), 0, s, (const typename C::elem*)prev,
+                       (const typename C::elem*)cur, L.N, L.plane, L.d, partials);
+    return hipGetLastError();
+  });
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(residual_final_kernel, dim3(1), dim3(256), 0, s, partials, blocks, result);
+  return hipGetLastError();
 }
 
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {

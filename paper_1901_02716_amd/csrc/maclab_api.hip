@@ -378,6 +378,43 @@ int maclab_diagnostics(maclab_t h, double out[7]) {
   return MACLAB_OK;
 }
 
+int maclab_residual(maclab_t h, double out[3]) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!out) return fail(h, MACLAB_EINVAL, "out is NULL");
+  HIP_TRY(h, launch_residual(h->L, h->state[h->cur ^ 1], h->state[h->cur], h->partials, h->result, h->stream));
+  double r[3];
+  HIP_TRY(h, hipMemcpyAsync(r, h->result, sizeof r, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  out[0] = r[0] * h->e;  // u = e u~
+  out[1] = r[1];
+  out[2] = r[2];
+  return MACLAB_OK;
+}
+
+int maclab_step_until(maclab_t h, double tol, int64_t max_steps, int64_t check_every, int64_t* done,
+                      double resid[3]) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!(tol >= 0) || max_steps < 0 || check_every < 1)
+    return fail(h, MACLAB_EINVAL, "need tol >= 0, max_steps >= 0 and check_every >= 1");
+  int64_t k = 0;
+  double r[3] = {0, 0, 0};
+  if (done) *done = 0;
+  while (k < max_steps) {
+    const int64_t m = std::min(check_every, max_steps - k);
+    int rc = maclab_step(h, m);
+    if (rc) return rc;
+    k += m;
+    if (done) *done = k;
+    rc = maclab_residual(h, r);
+    if (rc) return rc;
+    if (resid)
+      for (int i = 0; i < 3; ++i) resid[i] = r[i];
+    if (r[2] > 0) return fail(h, MACLAB_ENONFINITE, "%.0f non-finite nodes after %lld steps", r[2], (long long)h->steps);
+    if (r[0] < tol) break;
+  }
+  return MACLAB_OK;
+}
+
 int maclab_step_checked(maclab_t h, int64_t n, int64_t check_every, int64_t* done) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
   if (check_every < 1) return fail(h, MACLAB_EINVAL, "check_every must be >= 1");

@@ -162,6 +162,24 @@ class Simulation:
         state_bytes()); the simulation's own state does not change."""
         _lib.check(self.lib.maclab_step_external(self.h, src.data_ptr(), dst.data_ptr(), int(step_index)), self.h)
 
+    def residual(self) -> tuple[float, float, int]:
+        """Change over the last step: (max |u(n) - u(n-1)|, max |rho(n) -
+        rho(n-1)|, non-finite nodes), physical units."""
+        out = (ctypes.c_double * 3)()
+        _lib.check(self.lib.maclab_residual(self.h, out), self.h)
+        return float(out[0]), float(out[1]), int(out[2])
+
+    def run_to_steady(self, tol: float, max_steps: int, check_every: int = 100) -> tuple[int, float]:
+        """Steps until the per-step change of u falls below `tol` (checked
+        every `check_every` steps) or `max_steps` steps are done. Returns the
+        steps taken and the last residual max |u(n) - u(n-1)|."""
+        done = ctypes.c_int64(0)
+        out = (ctypes.c_double * 3)()
+        rc = self.lib.maclab_step_until(self.h, float(tol), int(max_steps), int(check_every), ctypes.byref(done),
+                                        out)
+        _lib.check(rc, self.h)
+        return int(done.value), float(out[0])
+
     def copy(self, src: torch.Tensor, dst: torch.Tensor, nbytes: int | None = None) -> None:
         """Streaming device copy on the simulation's stream (calibration: the
         memory rate of a step without its arithmetic)."""

@@ -481,3 +481,45 @@ def test_adjoint_force_closed_form(oracle_lib):
     dt = oracle.time_step(case.nu, case.dx)
     assert gG[0] == pytest.approx(2 * steps * dt * u[0].sum(), rel=1e-12)
     assert abs(gG[1]) < 1e-12
+
+
+# ------------------------------------------------------- steady-state residual
+
+def test_residual_matches_transient_series(oracle_lib):
+    """The change over one step of the channel started from rest is the
+    difference of two terms of the exact series above: max_j |sum_m a_m
+    lambda_m^n (lambda_m - 1) sin(pi m j / M)|; the density does not change."""
+    nu, u0, dpdx, n = 0.001, 0.1, -1e-4, 300
+    case = workloads.channel(nu=nu, u0=u0, dpdx=dpdx)
+    rho_a, u_a = _run(case, n)
+    rho_b, u_b = oracle.run(to_problem(case), rho_a, u_a, 1)
+    ru, rr = oracle.residual(rho_a, u_a, rho_b, u_b)
+    M = case.n[1] - 1
+    U = workloads.channel_profile(case, u0, dpdx)
+    j = np.arange(M + 1)
+    dev0 = -U
+    dev0[0] = dev0[M] = 0.0
+    diff = np.zeros(M + 1)
+    for m in range(1, M):
+        s = np.sin(np.pi * m * j / M)
+        lam = (2 + math.cos(math.pi * m / M)) / 3
+        diff += 2.0 / M * np.sum(dev0 * s) * lam ** n * (lam - 1) * s
+    e = oracle.particle_speed(nu, case.dx)
+    assert abs(ru - np.abs(diff).max()) < (n + 1) * 4.4e-16 * e
+    assert rr < (n + 1) * 2.2e-16
+    assert oracle.residual(rho_a, u_a, rho_a, u_a) == (0.0, 0.0)
+
+
+def test_residual_decays_at_the_slowest_mode(oracle_lib):
+    """Late in the transient the residual shrinks by lambda_1 = (2 + cos(pi /
+    M)) / 3 per step: the rate a steady-state driver observes."""
+    case = workloads.channel(nu=0.01, u0=0.1, dpdx=0.0)
+    n, k = 6000, 400
+    p = to_problem(case)
+    rho, u = _run(case, n)
+    r1 = oracle.residual(rho, u, *oracle.run(p, rho, u, 1))[0]
+    rho2, u2 = oracle.run(p, rho, u, k)
+    r2 = oracle.residual(rho2, u2, *oracle.run(p, rho2, u2, 1))[0]
+    M = case.n[1] - 1
+    lam = (2 + math.cos(math.pi / M)) / 3
+    assert r2 / r1 == pytest.approx(lam ** k, rel=1e-3)
