@@ -335,6 +335,7 @@ def main(argv=None):
     ap.add_argument("--variants", default="s16,hilo", help="extra storage variants to time ('' for none)")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-steady", action="store_true", help="skip the steady-state run of the 2-D cavity")
     ap.add_argument("--no-autotune", action="store_true", help="use the default tiling")
     ap.add_argument("--tiling", default="", help="W,nyb,nzb,pf[,kernel] of the fast kernel (skips autotuning)")
     ap.add_argument("--adjoint-steps", type=int, default=2000,
@@ -383,7 +384,7 @@ def main(argv=None):
     adjoint = time_adjoint(args.adjoint_steps) if args.adjoint_steps > 0 else None
     batch = time_batch(args.batch_steps, max(10, args.batch_steps // 4)) if args.batch_steps > 0 else None
     small = time_small() if args.batch_steps > 0 else None
-    steady = time_steady() if args.batch_steps > 0 else None
+    steady = time_steady() if args.batch_steps > 0 and not args.no_steady else None
 
     cpu = None
     if not args.no_cpu_baseline:
