@@ -113,7 +113,10 @@ int make_layout(const maclab_config* c, Layout* L, std::string* why) {
     *why = "D2Q9 needs n[2] == 1";
     return MACLAB_EINVAL;
   }
-  const int64_t N = c->n[0] * c->n[1] * c->n[2];
+  // each count is at most 2^24, so n[0] n[1] fits; test it before the third
+  // factor can overflow
+  const int64_t nxy = c->n[0] * c->n[1];
+  const int64_t N = nxy > (int64_t(1) << 34) ? nxy : nxy * c->n[2];
   if (N > (int64_t(1) << 34)) {
     *why = "lattice too large";
     return MACLAB_EINVAL;

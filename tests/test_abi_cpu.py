@@ -65,6 +65,8 @@ def test_workspace_bytes():
     (dict(rho_ref=0.0), _lib.EINVAL),
     (dict(n=(0, 4, 4)), _lib.EINVAL),
     (dict(lattice=9, n=(8, 8, 2)), _lib.EINVAL),
+    (dict(n=(1 << 24, 1 << 24, 1 << 24)), _lib.EINVAL),  # node count overflows int64
+    (dict(n=(1 << 24, 1 << 11, 1 << 0)), _lib.EINVAL),   # 2^35 nodes
     (dict(), _lib.EWORKSPACE),                      # no workspace
     (dict(workspace=4096, workspace_bytes=16), _lib.EWORKSPACE),  # too small
     (dict(workspace=4100, workspace_bytes=1 << 40), _lib.EWORKSPACE),  # misaligned
