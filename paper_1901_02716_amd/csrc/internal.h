@@ -34,6 +34,14 @@ struct Layout {
 constexpr int kDiagBlocks = 1024;  // partial sums of the diagnostics reduction
 constexpr int kDiagValues = 8;     // M, Px, Py, Pz, E, max|u~|, non-finite, pad
 
+// Workgroups of 256 for a per-element kernel over `count` elements. A grid
+// dimension holds fewer than 2^32 work-items, and lattices may have more
+// nodes, so these kernels stride over the elements and the grid is capped.
+inline unsigned blocks_256(int64_t count) {
+  const int64_t b = (count + 255) / 256;
+  return (unsigned)(b < (int64_t(1) << 20) ? (b > 0 ? b : 1) : (int64_t(1) << 20));
+}
+
 // Launchers (kernels_generic.hip). All enqueue on `s` and return the launch
 // status.
 hipError_t launch_step_generic(const Layout& L, const void* src, void* dst, const StepParams& p,

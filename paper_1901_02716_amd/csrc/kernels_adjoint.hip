@@ -357,21 +357,21 @@ __global__ void adjoint_seed_kernel(const typename C::elem* __restrict__ sT, con
                                     typename C::T* __restrict__ adj, StepParams p, int d, double e) {
   using T = typename C::T;
   const int64_t N = p.nx * p.ny * p.nz;
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= N) return;
-  const int64_t i = x % p.nx, j = (x / p.nx) % p.ny, k = x / (p.nx * p.ny);
-  if (node_fixed(p, i, j, k)) {
-    for (int c = 0; c <= d; ++c) adj[c * p.plane + x] = (T)0;
-    return;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = x % p.nx, j = (x / p.nx) % p.ny, k = x / (p.nx * p.ny);
+    if (node_fixed(p, i, j, k)) {
+      for (int c = 0; c <= d; ++c) adj[c * p.plane + x] = (T)0;
+      continue;
+    }
+    const T inv = (T)1 / ((T)p.rho_ref + C::dec(sT[x], 0));
+    T R = 0;
+    for (int c = 0; c < d; ++c) {
+      const T M = (T)(e * dLdu[c * N + x]) * inv;
+      adj[(1 + c) * p.plane + x] = M;
+      R -= M * C::dec(sT[(1 + c) * p.plane + x], 1 + c);
+    }
+    adj[x] = R;
   }
-  const T inv = (T)1 / ((T)p.rho_ref + C::dec(sT[x], 0));
-  T R = 0;
-  for (int c = 0; c < d; ++c) {
-    const T M = (T)(e * dLdu[c * N + x]) * inv;
-    adj[(1 + c) * p.plane + x] = M;
-    R -= M * C::dec(sT[(1 + c) * p.plane + x], 1 + c);
-  }
-  adj[x] = R;
 }
 
 // dL/du0 = rho Mbar / e, dL/drho0 = Rbar + Mbar . u~ (FP64, SoA as the fields).
@@ -379,16 +379,16 @@ template <class C>
 __global__ void adjoint_result_kernel(const typename C::elem* __restrict__ s0, const typename C::T* __restrict__ adj,
                                       double* __restrict__ dLdu, double* __restrict__ dLdrho, int64_t N,
                                       int64_t plane, int d, double rho_ref, double e) {
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= N) return;
-  const double rho = rho_ref + (double)C::dec(s0[x], 0);
-  double rb = (double)adj[x];
-  for (int c = 0; c < d; ++c) {
-    const double M = (double)adj[(1 + c) * plane + x];
-    dLdu[c * N + x] = rho * M / e;
-    rb += M * (double)C::dec(s0[(1 + c) * plane + x], 1 + c);
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += (int64_t)gridDim.x * blockDim.x) {
+    const double rho = rho_ref + (double)C::dec(s0[x], 0);
+    double rb = (double)adj[x];
+    for (int c = 0; c < d; ++c) {
+      const double M = (double)adj[(1 + c) * plane + x];
+      dLdu[c * N + x] = rho * M / e;
+      rb += M * (double)C::dec(s0[(1 + c) * plane + x], 1 + c);
+    }
+    if (dLdrho) dLdrho[x] = rb;
   }
-  if (dLdrho) dLdrho[x] = rb;
 }
 
 // Folds the slots in a fixed order: out[c] = sum_b slots[b][c].
@@ -409,8 +409,8 @@ __global__ __launch_bounds__(256) void adjoint_fold_kernel(const double* __restr
 
 // Clears FP64 accumulators with a kernel (no memset node when captured).
 __global__ void zero_doubles_kernel(double* __restrict__ dst, int64_t count) {
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x < count) dst[x] = 0.0;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < count; x += (int64_t)gridDim.x * blockDim.x)
+    dst[x] = 0.0;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -502,7 +502,7 @@ hipError_t launch_adjoint_fast2d(const Layout& L, const void* sn, const void* an
 
 hipError_t launch_adjoint_seed(const Layout& L, const void* sT, const double* dLdu, void* adj, const StepParams& p,
                                double e, hipStream_t s) {
-  const unsigned blocks = (unsigned)((L.N + 255) / 256);
+  const unsigned blocks = blocks_256(L.N);
   return by_codec(L.precision, [&](auto codec) {
     using C = decltype(codec);
     hipLaunchKernelGGL(adjoint_seed_kernel<C>, dim3(blocks), dim3(256), 0, s, (const typename C::elem*)sT, dLdu,
@@ -513,7 +513,7 @@ hipError_t launch_adjoint_seed(const Layout& L, const void* sT, const double* dL
 
 hipError_t launch_adjoint_result(const Layout& L, const void* s0, const void* adj, double* dLdu, double* dLdrho,
                                  double rho_ref, double e, hipStream_t s) {
-  const unsigned blocks = (unsigned)((L.N + 255) / 256);
+  const unsigned blocks = blocks_256(L.N);
   return by_codec(L.precision, [&](auto codec) {
     using C = decltype(codec);
     hipLaunchKernelGGL(adjoint_result_kernel<C>, dim3(blocks), dim3(256), 0, s, (const typename C::elem*)s0,
@@ -529,7 +529,7 @@ hipError_t launch_adjoint_fold(const double* slots, int64_t nslots, double* out,
 
 hipError_t launch_zero_doubles(double* dst, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(zero_doubles_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, dst, count);
+  hipLaunchKernelGGL(zero_doubles_kernel, dim3(blocks_256(count)), dim3(256), 0, s, dst, count);
   return hipGetLastError();
 }
 

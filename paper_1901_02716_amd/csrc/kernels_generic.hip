@@ -87,23 +87,24 @@ __global__ __launch_bounds__(256) void step_generic_kernel(const typename C::ele
 template <class C>
 __global__ void impose_bc_kernel(typename C::elem* b0, typename C::elem* b1, int64_t nx, int64_t ny,
                                  int64_t nz, int64_t plane, int d, FaceValues fv, double rho_ref, double e) {
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= nx * ny * nz) return;
-  const int64_t idx[3] = {x % nx, (x / nx) % ny, x / (nx * ny)};
+  const int64_t N = nx * ny * nz;
   const int64_t n[3] = {nx, ny, nz};
-  int face = -1;
-  for (int f = 0; f < 6 && face < 0; ++f) {
-    if (fv.kind[f] != MACLAB_BC_FIXED) continue;
-    const int ax = f / 2;
-    if (idx[ax] == ((f & 1) ? n[ax] - 1 : 0)) face = f;
-  }
-  if (face < 0) return;
-  typename C::elem v[4];
-  v[0] = C::enc_nearest((typename C::T)(fv.rho[face] - rho_ref), 0);
-  for (int c = 0; c < d; ++c) v[1 + c] = C::enc_nearest((typename C::T)(fv.u[face][c] / e), 1 + c);
-  for (int f = 0; f <= d; ++f) {
-    b0[f * plane + x] = v[f];
-    b1[f * plane + x] = v[f];
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t idx[3] = {x % nx, (x / nx) % ny, x / (nx * ny)};
+    int face = -1;
+    for (int f = 0; f < 6 && face < 0; ++f) {
+      if (fv.kind[f] != MACLAB_BC_FIXED) continue;
+      const int ax = f / 2;
+      if (idx[ax] == ((f & 1) ? n[ax] - 1 : 0)) face = f;
+    }
+    if (face < 0) continue;
+    typename C::elem v[4];
+    v[0] = C::enc_nearest((typename C::T)(fv.rho[face] - rho_ref), 0);
+    for (int c = 0; c < d; ++c) v[1 + c] = C::enc_nearest((typename C::T)(fv.u[face][c] / e), 1 + c);
+    for (int f = 0; f <= d; ++f) {
+      b0[f * plane + x] = v[f];
+      b1[f * plane + x] = v[f];
+    }
   }
 }
 
@@ -111,18 +112,16 @@ __global__ void impose_bc_kernel(typename C::elem* b0, typename C::elem* b1, int
 template <class C>
 __global__ void encode_kernel(typename C::elem* dst, const double* __restrict__ src, int64_t count,
                               double offset, double mul, int field) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  dst[i] = C::enc_nearest((typename C::T)((src[i] - offset) * mul), field);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = C::enc_nearest((typename C::T)((src[i] - offset) * mul), field);
 }
 
 // Stored -> physical float64: dst = offset + mul * value.
 template <class C>
 __global__ void decode_kernel(double* dst, const typename C::elem* __restrict__ src, int64_t count,
                               double offset, double mul, int field) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  dst[i] = offset + mul * (double)C::dec(src[i], field);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = offset + mul * (double)C::dec(src[i], field);
 }
 
 // ------------------------------------------------------------ diagnostics
@@ -300,7 +299,7 @@ hipError_t launch_step_generic(const Layout& L, const void* src, void* dst, cons
 
 hipError_t launch_impose_bc(const Layout& L, void* b0, void* b1, const FaceValues& fv, double rho_ref,
                             double e, hipStream_t s) {
-  const unsigned blocks = (unsigned)((L.N + 255) / 256);
+  const unsigned blocks = blocks_256(L.N);
   return dispatch_codec(L.precision, [&](auto codec) {
     using C = decltype(codec);
     using E = typename C::elem;
@@ -313,7 +312,7 @@ hipError_t launch_impose_bc(const Layout& L, void* b0, void* b1, const FaceValue
 hipError_t launch_encode(const Layout& L, void* dst, const double* src, int64_t count, double offset,
                          double mul, int field, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((count + 255) / 256);
+  const unsigned blocks = blocks_256(count);
   return dispatch_codec(L.precision, [&](auto codec) {
     using C = decltype(codec);
     hipLaunchKernelGGL((encode_kernel<C>), dim3(blocks), dim3(256), 0, s, (typename C::elem*)dst, src,
@@ -325,7 +324,7 @@ hipError_t launch_encode(const Layout& L, void* dst, const double* src, int64_t 
 hipError_t launch_decode(const Layout& L, double* dst, const void* src, int64_t count, double offset,
                          double mul, int field, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((count + 255) / 256);
+  const unsigned blocks = blocks_256(count);
   return dispatch_codec(L.precision, [&](auto codec) {
     using C = decltype(codec);
     hipLaunchKernelGGL((decode_kernel<C>), dim3(blocks), dim3(256), 0, s, dst,
