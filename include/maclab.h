@@ -138,9 +138,12 @@ int maclab_diagnostics(maclab_t h, double out[7]);
 int maclab_params(maclab_t h, double out[6]);
 
 /* Native state: the d+1 stored planes of the current step in storage format,
- * maclab_state_bytes(h) bytes. A plane holds the N nodes followed by padding
- * (a plane stride of N rounded up to 512, plus 256 elements); the library
- * never reads the padding, and keeps it zero in its own buffers. save copies it to caller device memory; load
+ * maclab_state_bytes(h) bytes. In a plane, node (i, j, k) sits at element
+ * i + px (j + ny k): px = nx for D3Q19, and for D2Q9 nx rounded up to a
+ * multiple of 128 bytes (so every row starts on a 128-byte boundary). The
+ * plane stride is px ny nz rounded up to 512, plus 256 elements. The library
+ * never reads the padding (row ends and plane ends) and keeps it zero in its
+ * own buffers. save copies the state to caller device memory; load
  * restores it bitwise into both ping-pong buffers (including 16-bit
  * storage), so a run resumed from a saved state repeats the original bit for
  * bit (for S16 the rounding stream is keyed by the step counter, which load
@@ -183,8 +186,9 @@ int maclab_autotune(maclab_t h, int reps, double* best_ms);
 int maclab_set_body_force(maclab_t h, const double* G);
 
 /* One step from the native state at src to dst (both caller-owned device
- * buffers of maclab_state_bytes; dst receives the fixed-face values too, and
- * its plane padding is left as it was),
+ * buffers of maclab_state_bytes; dst receives the fixed-face values too; the
+ * padding at plane ends is left as it was, and a D2Q9 row's padding may
+ * receive src's),
  * with the rounding stream of step `step_index`. The handle's own state and
  * step counter are untouched. Used to recompute a trajectory segment from a
  * checkpoint. */

@@ -40,6 +40,7 @@ struct Lattice<19> {
 // of the body force (test 2 of the paper, with G = -dp/dx).
 struct StepParams {
   int64_t nx, ny, nz;   // node counts
+  int64_t px;           // elements between consecutive rows (>= nx)
   int64_t plane;        // elements between consecutive planes of one buffer
   int fixed[3];         // 1 if both faces of the axis are fixed (Dirichlet)
   double rho_ref;       // density the stored deviation refers to
@@ -48,6 +49,14 @@ struct StepParams {
   uint64_t step;        // index of the step being computed
   uint32_t sr_key;      // sr_key(seed, step): rounding key of this step
 };
+
+// Node (i, j, k) is stored at i + px (j + ny k). The dense index d = i + nx (j
+// + ny k) numbers the nodes without the row padding (the order of the fields
+// a caller passes in and gets back, and the node numbers of the stochastic
+// rounding); this returns the stored position of dense index d.
+__device__ __forceinline__ int64_t stored_index(int64_t d, int64_t nx, int64_t px) {
+  return px == nx ? d : (d / nx) * px + d % nx;
+}
 
 // --------------------------------------------------------- storage codecs
 // A codec maps the compute type T to the stored element and back. Field index

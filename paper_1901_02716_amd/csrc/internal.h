@@ -23,7 +23,8 @@ struct FaceValues {
 struct Layout {
   int q = 0, d = 0, precision = 0, bytes = 0;
   int64_t nx = 0, ny = 0, nz = 0, N = 0;
-  int64_t plane = 0;          // elements between field planes (N rounded up, plus 256)
+  int64_t px = 0;             // elements between rows (nx, or nx rounded up to 128 bytes for D2Q9)
+  int64_t plane = 0;          // elements between field planes (px ny nz rounded up, plus 256)
   size_t state_bytes = 0;     // (d + 1) planes
   size_t partial_bytes = 0;   // reduction partials
   size_t staging_bytes = 0;   // host transfer staging
@@ -48,10 +49,12 @@ hipError_t launch_step_generic(const Layout& L, const void* src, void* dst, cons
                                hipStream_t s);
 hipError_t launch_impose_bc(const Layout& L, void* buf0, void* buf1, const FaceValues& fv, double rho_ref,
                             double e, hipStream_t s);
-hipError_t launch_encode(const Layout& L, void* plane_dst, const double* src, int64_t count, double offset,
-                         double mul, int field, hipStream_t s);
-hipError_t launch_decode(const Layout& L, double* dst, const void* plane_src, int64_t count, double offset,
-                         double mul, int field, hipStream_t s);
+// Dense nodes first .. first+count-1 of one field plane (dense index: x
+// fastest over nx, no row padding) from / to FP64 arrays of count values.
+hipError_t launch_encode(const Layout& L, void* plane_dst, const double* src, int64_t first, int64_t count,
+                         double offset, double mul, int field, hipStream_t s);
+hipError_t launch_decode(const Layout& L, double* dst, const void* plane_src, int64_t first, int64_t count,
+                         double offset, double mul, int field, hipStream_t s);
 // Largest change of u~ and of drho from state `prev` to state `cur` and the
 // count of non-finite nodes in `cur`, into result[0..2] (FP64, in storage
 // units); partials holds kDiagBlocks x 4 doubles.
@@ -98,15 +101,13 @@ hipError_t launch_step_fast2d(const Layout& L, const void* src, void* dst, const
 struct Lattice2D {
   int nx, ny, pitch;  // node counts; elements between rows (>= nx)
   int xper, yper;     // periodic axes (else both faces fixed)
-  int aligned;        // rows start on a KX-element boundary (vector loads)
   double gx, gy;      // dt G / e
   int64_t base;       // element offset of the lattice's first field plane
   int64_t plane;      // elements between field planes
 };
 // A batch step: work item {lattice, x0, y0, y1} of a device table, one
-// wavefront each, all lattices in one launch. vec: every lattice of the items
-// has rows that start on a kx-element boundary (x extent a multiple of kx).
-hipError_t launch_step_fast2d_items(int precision, int kx, bool vec, const void* src, void* dst, const Lattice2D* lat,
+// wavefront each, all lattices in one launch (every pitch a multiple of kx).
+hipError_t launch_step_fast2d_items(int precision, int kx, const void* src, void* dst, const Lattice2D* lat,
                                     const int4* items, int nitems, double rho_ref, uint32_t sr_key, hipStream_t s);
 
 // Reverse mode (kernels_adjoint.hip). Adjoint buffers hold (Rbar, Mbar) in

@@ -87,9 +87,10 @@ struct Occupancy2D {
 // loads and stores in every row step: lanes without a node (past the end of
 // the row, the halo of an interior lane, a row past the band) use an
 // out-of-range offset. The compiler's wait for a row's loads then only has to
-// let the previous row's stores stay in flight. VEC: rows start on a KX-element
-// boundary, so a lane moves its KX nodes with one vector access per field.
-template <class C, int KX, bool VEC>
+// let the previous row's stores stay in flight. Rows start on a boundary of
+// at least 128 bytes (the row pitch), so a lane moves its KX nodes with one
+// vector access per field.
+template <class C, int KX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy2D<C, KX>::value)))
 void step_d2q9_fast(const typename C::elem* __restrict__ src, typename C::elem* __restrict__ dst, Fast2DParams p) {
   using T = typename C::T;
@@ -149,18 +150,9 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src, typename C::elem* 
   E hring[3][3];
   auto load_row = [&](int y, bool valid, V (&ld)[3], E (&hld)[3]) {
     const int rb = (int)((int64_t)lt.pitch * ywrap(y) * EB);
-    if constexpr (VEC) {
-      const int off = valid && xb < lt.nx ? rb + xb * EB : kOutOfRange;
+    const int off = valid && xb < lt.nx ? rb + xb * EB : kOutOfRange;
 #pragma unroll
-      for (int f = 0; f < 3; ++f) ld[f] = buf_load<V>(rs[f], off);
-    } else {
-#pragma unroll
-      for (int e = 0; e < KX; ++e) {
-        const int off = valid && xb + e < lt.nx ? rb + (xb + e) * EB : kOutOfRange;
-#pragma unroll
-        for (int f = 0; f < 3; ++f) ld[f].v[e] = buf_load<E>(rs[f], off);
-      }
-    }
+    for (int f = 0; f < 3; ++f) ld[f] = buf_load<V>(rs[f], off);
     const int hoff = valid && halo_lane ? rb + hx * EB : kOutOfRange;
 #pragma unroll
     for (int f = 0; f < 3; ++f) hld[f] = buf_load<E>(rs[f], hoff);
@@ -265,34 +257,24 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src, typename C::elem* 
       const T vx = (am.mx[q] + (T)(36.0 * lt.gx)) * inv;
       const T vy = (am.my[q] + (T)(36.0 * lt.gy)) * inv;
       uint32_t bits = 0;
-      if constexpr (needs_rng<C>::value) bits = sr_node_bits(p.sr_key, (int64_t)lt.pitch * ywrap(yd) + xb + q);
+      if constexpr (needs_rng<C>::value) bits = sr_node_bits(p.sr_key, (int64_t)lt.nx * ywrap(yd) + xb + q);
       o[0].v[q] = C::enc(drn, 0, bits);
       o[1].v[q] = C::enc(vx, 1, bits);
       o[2].v[q] = C::enc(vy, 2, bits);
     }
-    if constexpr (VEC) {
-      // a wall node keeps its stored value (the row before holds it unchanged)
+    // a wall node keeps its stored value (the row before holds it unchanged),
+    // and so does the row padding a lane's last nodes may reach
 #pragma unroll
-      for (int q = 0; q < KX; ++q) {
-        const int x = xb + q;
-        if (!lt.xper && (x == 0 || x == lt.nx - 1)) {
+    for (int q = 0; q < KX; ++q) {
+      const int x = xb + q;
+      if (x >= lt.nx || (!lt.xper && (x == 0 || x == lt.nx - 1))) {
 #pragma unroll
-          for (int f = 0; f < 3; ++f) o[f].v[q] = prev[f].v[q];
-        }
-      }
-      const int off = STORE && xb < lt.nx ? rb + xb * EB : kOutOfRange;
-#pragma unroll
-      for (int f = 0; f < 3; ++f) buf_store<V>(o[f], rd[f], off);
-    } else {
-#pragma unroll
-      for (int q = 0; q < KX; ++q) {
-        const int x = xb + q;
-        const bool node = STORE && x < lt.nx && (lt.xper || (x != 0 && x != lt.nx - 1));
-        const int off = node ? rb + x * EB : kOutOfRange;
-#pragma unroll
-        for (int f = 0; f < 3; ++f) buf_store<E>(o[f].v[q], rd[f], off);
+        for (int f = 0; f < 3; ++f) o[f].v[q] = prev[f].v[q];
       }
     }
+    const int off = STORE && xb < lt.nx ? rb + xb * EB : kOutOfRange;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) buf_store<V>(o[f], rd[f], off);
   };
 
   using NoStore = std::integral_constant<bool, false>;
@@ -330,6 +312,7 @@ static bool kx_ok(int kx) { return kx == 1 || kx == 2; }
 
 bool fast2d_shape_valid(const Layout& L, const StepParams& p, const Fast2DShape& sh) {
   if (!kx_ok(sh.kx) || sh.nband < 1) return false;
+  if (L.px % sh.kx != 0) return false;  // a lane's KX nodes are one vector access
   const int nyo = p.fixed[1] ? (int)L.ny - 2 : (int)L.ny;
   if (sh.nband > nyo) return false;
   if (!p.fixed[0] && L.nx % (64 * sh.kx) != 0) return false;
@@ -368,34 +351,33 @@ int fast2d_candidates(const Layout& L, const StepParams& p, int cus, Fast2DShape
   return n;
 }
 
-template <class C, int KX, bool VEC>
+template <class C, int KX>
 static hipError_t launch2d_kx(const void* src, void* dst, const Fast2DParams& fp, hipStream_t s) {
   using E = typename C::elem;
   const unsigned blocks = (unsigned)((fp.nitems + 3) / 4);
-  hipLaunchKernelGGL((step_d2q9_fast<C, KX, VEC>), dim3(blocks), dim3(256), 0, s, (const E*)src, (E*)dst, fp);
+  hipLaunchKernelGGL((step_d2q9_fast<C, KX>), dim3(blocks), dim3(256), 0, s, (const E*)src, (E*)dst, fp);
   return hipGetLastError();
 }
 
 template <class C>
-static hipError_t launch2d_codec(int kx, bool vec, const void* src, void* dst, const Fast2DParams& fp,
-                                 hipStream_t s) {
-  if (kx == 1) return launch2d_kx<C, 1, true>(src, dst, fp, s);
-  if (kx == 2) return vec ? launch2d_kx<C, 2, true>(src, dst, fp, s) : launch2d_kx<C, 2, false>(src, dst, fp, s);
+static hipError_t launch2d_codec(int kx, const void* src, void* dst, const Fast2DParams& fp, hipStream_t s) {
+  if (kx == 1) return launch2d_kx<C, 1>(src, dst, fp, s);
+  if (kx == 2) return launch2d_kx<C, 2>(src, dst, fp, s);
   return hipErrorInvalidValue;
 }
 
-static hipError_t launch2d(int precision, int kx, bool vec, const void* src, void* dst, const Fast2DParams& fp,
+static hipError_t launch2d(int precision, int kx, const void* src, void* dst, const Fast2DParams& fp,
                            hipStream_t s) {
   switch (precision) {
-    case MACLAB_FP64: return launch2d_codec<CodecF64>(kx, vec, src, dst, fp, s);
-    case MACLAB_FP32: return launch2d_codec<CodecF32>(kx, vec, src, dst, fp, s);
-    case MACLAB_HILO: return launch2d_codec<CodecHILO>(kx, vec, src, dst, fp, s);
-    case MACLAB_S16: return launch2d_codec<CodecS16>(kx, vec, src, dst, fp, s);
+    case MACLAB_FP64: return launch2d_codec<CodecF64>(kx, src, dst, fp, s);
+    case MACLAB_FP32: return launch2d_codec<CodecF32>(kx, src, dst, fp, s);
+    case MACLAB_HILO: return launch2d_codec<CodecHILO>(kx, src, dst, fp, s);
+    case MACLAB_S16: return launch2d_codec<CodecS16>(kx, src, dst, fp, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_step_fast2d_items(int precision, int kx, bool vec, const void* src, void* dst, const Lattice2D* lat,
+hipError_t launch_step_fast2d_items(int precision, int kx, const void* src, void* dst, const Lattice2D* lat,
                                     const int4* items, int nitems, double rho_ref, uint32_t sr_key, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   Fast2DParams fp{};
@@ -406,7 +388,7 @@ hipError_t launch_step_fast2d_items(int precision, int kx, bool vec, const void*
   fp.nband = 1;
   fp.rho_ref = rho_ref;
   fp.sr_key = sr_key;
-  return launch2d(precision, kx, vec, src, dst, fp, s);
+  return launch2d(precision, kx, src, dst, fp, s);
 }
 
 hipError_t launch_step_fast2d(const Layout& L, const void* src, void* dst, const StepParams& p,
@@ -418,14 +400,13 @@ hipError_t launch_step_fast2d(const Layout& L, const void* src, void* dst, const
   Lattice2D& lt = fp.one;
   lt.nx = (int)L.nx;
   lt.ny = (int)L.ny;
-  lt.pitch = (int)L.nx;
+  lt.pitch = (int)L.px;
   lt.xper = !p.fixed[0];
   lt.yper = !p.fixed[1];
   lt.gx = p.g[0];
   lt.gy = p.g[1];
   lt.base = 0;
   lt.plane = L.plane;
-  lt.aligned = (L.nx % sh.kx) == 0;
   fp.nseg = (int)((L.nx + 64 * sh.kx - 1) / (64 * sh.kx));
   fp.nyo = p.fixed[1] ? lt.ny - 2 : lt.ny;
   fp.ylo = p.fixed[1] ? 1 : 0;
@@ -433,7 +414,7 @@ hipError_t launch_step_fast2d(const Layout& L, const void* src, void* dst, const
   fp.nitems = fp.nseg * fp.nband;
   fp.rho_ref = p.rho_ref;
   fp.sr_key = p.sr_key;
-  return launch2d(L.precision, sh.kx, lt.aligned != 0, src, dst, fp, s);
+  return launch2d(L.precision, sh.kx, src, dst, fp, s);
 }
 
 }  // namespace maclab

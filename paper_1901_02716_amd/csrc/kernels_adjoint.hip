@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void adjoint_generic_kernel(const typename C::
 
   double gpart[3] = {0, 0, 0};
   if (inside) {
-    const int64_t y = i + p.nx * (j + p.ny * k);
+    const int64_t y = i + p.px * (j + p.ny * k);
 #pragma unroll
     for (int c = 0; c < D; ++c) gpart[c] = (double)bn1[(1 + c) * p.plane + y];
     T rb = 0, mb[3] = {0, 0, 0}, u[3] = {0, 0, 0};
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void adjoint_generic_kernel(const typename C::
       for (int a = 0; a < Q; ++a) {
         const int cx = Lat::cx[a], cy = Lat::cy[a], cz = Lat::cz[a];
         // a non-fixed node has all its neighbours on the lattice (or wrapped)
-        const int64_t x = wrap(i + cx, p.nx) + p.nx * (wrap(j + cy, p.ny) + p.ny * wrap(k + cz, p.nz));
+        const int64_t x = wrap(i + cx, p.nx) + p.px * (wrap(j + cy, p.ny) + p.ny * wrap(k + cz, p.nz));
         T Fb = bn1[x];
         if (cx) Fb += (T)cx * bn1[p.plane + x];
         if (cy) Fb += (T)cy * bn1[2 * p.plane + x];
@@ -126,6 +126,7 @@ __global__ __launch_bounds__(256) void adjoint_generic_kernel(const typename C::
 // Every row of the lattice is written, fixed rows and columns with zeros.
 struct Adj2DParams {
   int nx, ny;
+  int64_t pitch;  // elements between rows
   int64_t plane;
   int xper, yper;
   int nseg, nband, nitems;
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(256) void adjoint_d2q9_fast(const typename C::elem*
     for (int e = 0; e < KX; ++e) P[e] = Mx[e] = My[e] = (T)0;
     hP = hMx = hMy = (T)0;
     if (!valid) return;  // outside a fixed face: nothing flows from there
-    const int64_t rb = (int64_t)p.nx * rr;
+    const int64_t rb = p.pitch * rr;
     if (vec) {
       using V = RowVecT<T, KX>;
       const V a = *reinterpret_cast<const V*>(bn1 + rb + xb);
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(256) void adjoint_d2q9_fast(const typename C::elem*
     }
   };
   auto load_u = [&](int j) {
-    const int64_t rb = (int64_t)p.nx * j;
+    const int64_t rb = p.pitch * j;
 #pragma unroll
     for (int e = 0; e < KX; ++e) {
       int x = xb + e;
@@ -285,7 +286,7 @@ __global__ __launch_bounds__(256) void adjoint_d2q9_fast(const typename C::elem*
     }
     if (complete) {
       const int j = r - 1;
-      const int64_t rb = (int64_t)p.nx * j;
+      const int64_t rb = p.pitch * j;
       const bool row_fixed = !p.yper && (j == 0 || j == p.ny - 1);
       RowVecT<T, KX> oR, oX, oY;
 #pragma unroll
@@ -357,8 +358,9 @@ __global__ void adjoint_seed_kernel(const typename C::elem* __restrict__ sT, con
                                     typename C::T* __restrict__ adj, StepParams p, int d, double e) {
   using T = typename C::T;
   const int64_t N = p.nx * p.ny * p.nz;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = x % p.nx, j = (x / p.nx) % p.ny, k = x / (p.nx * p.ny);
+  for (int64_t di = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; di < N; di += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = di % p.nx, j = (di / p.nx) % p.ny, k = di / (p.nx * p.ny);
+    const int64_t x = stored_index(di, p.nx, p.px);
     if (node_fixed(p, i, j, k)) {
       for (int c = 0; c <= d; ++c) adj[c * p.plane + x] = (T)0;
       continue;
@@ -366,7 +368,7 @@ __global__ void adjoint_seed_kernel(const typename C::elem* __restrict__ sT, con
     const T inv = (T)1 / ((T)p.rho_ref + C::dec(sT[x], 0));
     T R = 0;
     for (int c = 0; c < d; ++c) {
-      const T M = (T)(e * dLdu[c * N + x]) * inv;
+      const T M = (T)(e * dLdu[c * N + di]) * inv;
       adj[(1 + c) * p.plane + x] = M;
       R -= M * C::dec(sT[(1 + c) * p.plane + x], 1 + c);
     }
@@ -378,16 +380,17 @@ __global__ void adjoint_seed_kernel(const typename C::elem* __restrict__ sT, con
 template <class C>
 __global__ void adjoint_result_kernel(const typename C::elem* __restrict__ s0, const typename C::T* __restrict__ adj,
                                       double* __restrict__ dLdu, double* __restrict__ dLdrho, int64_t N,
-                                      int64_t plane, int d, double rho_ref, double e) {
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += (int64_t)gridDim.x * blockDim.x) {
+                                      int64_t nx, int64_t px, int64_t plane, int d, double rho_ref, double e) {
+  for (int64_t di = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; di < N; di += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = stored_index(di, nx, px);
     const double rho = rho_ref + (double)C::dec(s0[x], 0);
     double rb = (double)adj[x];
     for (int c = 0; c < d; ++c) {
       const double M = (double)adj[(1 + c) * plane + x];
-      dLdu[c * N + x] = rho * M / e;
+      dLdu[c * N + di] = rho * M / e;
       rb += M * (double)C::dec(s0[(1 + c) * plane + x], 1 + c);
     }
-    if (dLdrho) dLdrho[x] = rb;
+    if (dLdrho) dLdrho[di] = rb;
   }
 }
 
@@ -478,13 +481,14 @@ hipError_t launch_adjoint_fast2d(const Layout& L, const void* sn, const void* an
   Adj2DParams ap{};
   ap.nx = (int)L.nx;
   ap.ny = (int)L.ny;
+  ap.pitch = L.px;
   ap.plane = L.plane;
   ap.xper = !p.fixed[0];
   ap.yper = !p.fixed[1];
   ap.nseg = (int)((L.nx + 64 * sh.kx - 1) / (64 * sh.kx));
   ap.nband = sh.nband;
   ap.nitems = ap.nseg * ap.nband;
-  ap.aligned = (L.nx % sh.kx) == 0;
+  ap.aligned = (L.px % sh.kx) == 0;
   const unsigned blocks = (unsigned)((ap.nitems + 3) / 4);
   return by_codec(L.precision, [&](auto codec) {
     using C = decltype(codec);
@@ -517,7 +521,7 @@ hipError_t launch_adjoint_result(const Layout& L, const void* s0, const void* ad
   return by_codec(L.precision, [&](auto codec) {
     using C = decltype(codec);
     hipLaunchKernelGGL(adjoint_result_kernel<C>, dim3(blocks), dim3(256), 0, s, (const typename C::elem*)s0,
-                       (const typename C::T*)adj, dLdu, dLdrho, L.N, L.plane, L.d, rho_ref, e);
+                       (const typename C::T*)adj, dLdu, dLdrho, L.N, L.nx, L.px, L.plane, L.d, rho_ref, e);
     return hipGetLastError();
   });
 }

@@ -694,6 +694,7 @@ bool fast_step_supported(const Layout& L, const StepParams& p) {
   if (L.q != 19) return false;
   if (L.precision != MACLAB_FP32 && L.precision != MACLAB_HILO && L.precision != MACLAB_S16) return false;
   if (L.nx != 64 && L.nx != 128 && L.nx != 256) return false;
+  if (L.px != L.nx) return false;  // rows are exactly one wavefront's nodes
   if (L.ny < 3 || L.nz < 3) return false;
   if (L.plane * L.bytes >= (int64_t(1) << 31)) return false;  // buffer offsets are 31-bit
   (void)p;

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void step_generic_kernel(const typename C::ele
     const int64_t si = wrap_idx(i - cx, p.nx);
     const int64_t sj = wrap_idx(j - cy, p.ny);
     const int64_t sk = wrap_idx(k - cz, p.nz);
-    const int64_t s = si + p.nx * (sj + p.ny * sk);
+    const int64_t s = si + p.px * (sj + p.ny * sk);
     const T dr = load_field<C>(src, p.plane, 0, s);
     const T ux = load_field<C>(src, p.plane, 1, s);
     const T uy = load_field<C>(src, p.plane, 2, s);
@@ -73,9 +73,9 @@ __global__ __launch_bounds__(256) void step_generic_kernel(const typename C::ele
   }
   // drho' = r / 36, u~' = (m + 36 g) / (36 rho_ref + r)
   const T inv = (T)1 / ((T)36 * rho_ref + drho);
-  const int64_t x = i + p.nx * (j + p.ny * k);
+  const int64_t x = i + p.px * (j + p.ny * k);
   uint32_t bits = 0;
-  if constexpr (needs_rng<C>::value) bits = sr_node_bits(p.sr_key, x);
+  if constexpr (needs_rng<C>::value) bits = sr_node_bits(p.sr_key, i + p.nx * (j + p.ny * k));
   store_field<C>(dst, p.plane, 0, x, div36(drho), bits);
   store_field<C>(dst, p.plane, 1, x, (mx + (T)(36.0 * p.g[0])) * inv, bits);
   store_field<C>(dst, p.plane, 2, x, (my + (T)(36.0 * p.g[1])) * inv, bits);
@@ -86,11 +86,13 @@ __global__ __launch_bounds__(256) void step_generic_kernel(const typename C::ele
 // faces takes the values of the lowest-numbered one.
 template <class C>
 __global__ void impose_bc_kernel(typename C::elem* b0, typename C::elem* b1, int64_t nx, int64_t ny,
-                                 int64_t nz, int64_t plane, int d, FaceValues fv, double rho_ref, double e) {
+                                 int64_t nz, int64_t px, int64_t plane, int d, FaceValues fv, double rho_ref,
+                                 double e) {
   const int64_t N = nx * ny * nz;
   const int64_t n[3] = {nx, ny, nz};
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t idx[3] = {x % nx, (x / nx) % ny, x / (nx * ny)};
+  for (int64_t di = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; di < N; di += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t idx[3] = {di % nx, (di / nx) % ny, di / (nx * ny)};
+    const int64_t x = stored_index(di, nx, px);
     int face = -1;
     for (int f = 0; f < 6 && face < 0; ++f) {
       if (fv.kind[f] != MACLAB_BC_FIXED) continue;
@@ -108,20 +110,22 @@ __global__ void impose_bc_kernel(typename C::elem* b0, typename C::elem* b1, int
   }
 }
 
-// Physical float64 -> stored: value = (src - offset) * mul, rounded to nearest.
+// Physical float64 -> stored: value = (src - offset) * mul, rounded to nearest;
+// src[i] is dense node first + i of the plane at dst.
 template <class C>
-__global__ void encode_kernel(typename C::elem* dst, const double* __restrict__ src, int64_t count,
-                              double offset, double mul, int field) {
+__global__ void encode_kernel(typename C::elem* dst, const double* __restrict__ src, int64_t first, int64_t count,
+                              int64_t nx, int64_t px, double offset, double mul, int field) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = C::enc_nearest((typename C::T)((src[i] - offset) * mul), field);
+    dst[stored_index(first + i, nx, px)] = C::enc_nearest((typename C::T)((src[i] - offset) * mul), field);
 }
 
-// Stored -> physical float64: dst = offset + mul * value.
+// Stored -> physical float64: dst = offset + mul * value; dst[i] is dense
+// node first + i of the plane at src.
 template <class C>
-__global__ void decode_kernel(double* dst, const typename C::elem* __restrict__ src, int64_t count,
-                              double offset, double mul, int field) {
+__global__ void decode_kernel(double* dst, const typename C::elem* __restrict__ src, int64_t first, int64_t count,
+                              int64_t nx, int64_t px, double offset, double mul, int field) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = offset + mul * (double)C::dec(src[i], field);
+    dst[i] = offset + mul * (double)C::dec(src[stored_index(first + i, nx, px)], field);
 }
 
 // ------------------------------------------------------------ diagnostics
@@ -143,11 +147,13 @@ __device__ __forceinline__ double wave_max(double v) {
 
 template <class C>
 __global__ __launch_bounds__(256) void diag_partial_kernel(const typename C::elem* __restrict__ s,
-                                                           int64_t N, int64_t plane, int d, double rho_ref,
-                                                           double e, double* __restrict__ partials) {
+                                                           int64_t N, int64_t nx, int64_t px, int64_t plane,
+                                                           int d, double rho_ref, double e,
+                                                           double* __restrict__ partials) {
   double acc[kDiagValues] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N;
-       x += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t di = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; di < N;
+       di += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = stored_index(di, nx, px);
     const double rho = rho_ref + (double)C::dec(s[x], 0);
     double ut[3] = {0, 0, 0};
     bool finite = isfinite(rho);
@@ -210,10 +216,12 @@ __global__ __launch_bounds__(256) void diag_final_kernel(const double* __restric
 template <class C>
 __global__ __launch_bounds__(256) void residual_partial_kernel(const typename C::elem* __restrict__ a,
                                                                const typename C::elem* __restrict__ b, int64_t N,
-                                                               int64_t plane, int d, double* __restrict__ partials) {
+                                                               int64_t nx, int64_t px, int64_t plane, int d,
+                                                               double* __restrict__ partials) {
   double du = 0, dr = 0, bad = 0;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N;
-       x += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t di = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; di < N;
+       di += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = stored_index(di, nx, px);
     const double rb = (double)C::dec(b[x], 0);
     bool finite = isfinite(rb);
     double m = 0;
@@ -304,31 +312,31 @@ hipError_t launch_impose_bc(const Layout& L, void* b0, void* b1, const FaceValue
     using C = decltype(codec);
     using E = typename C::elem;
     hipLaunchKernelGGL((impose_bc_kernel<C>), dim3(blocks), dim3(256), 0, s, (E*)b0, (E*)b1, L.nx, L.ny,
-                       L.nz, L.plane, L.d, fv, rho_ref, e);
+                       L.nz, L.px, L.plane, L.d, fv, rho_ref, e);
     return hipGetLastError();
   });
 }
 
-hipError_t launch_encode(const Layout& L, void* dst, const double* src, int64_t count, double offset,
-                         double mul, int field, hipStream_t s) {
+hipError_t launch_encode(const Layout& L, void* dst, const double* src, int64_t first, int64_t count,
+                         double offset, double mul, int field, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const unsigned blocks = blocks_256(count);
   return dispatch_codec(L.precision, [&](auto codec) {
     using C = decltype(codec);
-    hipLaunchKernelGGL((encode_kernel<C>), dim3(blocks), dim3(256), 0, s, (typename C::elem*)dst, src,
-                       count, offset, mul, field);
+    hipLaunchKernelGGL((encode_kernel<C>), dim3(blocks), dim3(256), 0, s, (typename C::elem*)dst, src, first,
+                       count, L.nx, L.px, offset, mul, field);
     return hipGetLastError();
   });
 }
 
-hipError_t launch_decode(const Layout& L, double* dst, const void* src, int64_t count, double offset,
-                         double mul, int field, hipStream_t s) {
+hipError_t launch_decode(const Layout& L, double* dst, const void* src, int64_t first, int64_t count,
+                         double offset, double mul, int field, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const unsigned blocks = blocks_256(count);
   return dispatch_codec(L.precision, [&](auto codec) {
     using C = decltype(codec);
     hipLaunchKernelGGL((decode_kernel<C>), dim3(blocks), dim3(256), 0, s, dst,
-                       (const typename C::elem*)src, count, offset, mul, field);
+                       (const typename C::elem*)src, first, count, L.nx, L.px, offset, mul, field);
     return hipGetLastError();
   });
 }
@@ -340,7 +348,7 @@ hipError_t launch_diagnostics(const Layout& L, const void* state, double rho_ref
   hipError_t err = dispatch_codec(L.precision, [&](auto codec) {
     using C = decltype(codec);
     hipLaunchKernelGGL((diag_partial_kernel<C>), dim3(blocks), dim3(256), 0, s,
-                       (const typename C::elem*)state, L.N, L.plane, L.d, rho_ref, e, partials);
+                       (const typename C::elem*)state, L.N, L.nx, L.px, L.plane, L.d, rho_ref, e, partials);
     return hipGetLastError();
   });
   if (err != hipSuccess) return err;
@@ -366,7 +374,7 @@ hipError_t launch_residual(const Layout& L, const void* prev, const void* cur, d
   hipError_t err = dispatch_codec(L.precision, [&](auto codec) {
     using C = decltype(codec);
     hipLaunchKernelGGL((residual_partial_kernel<C>), dim3(blocks), dim3(256), 0, s, (const typename C::elem*)prev,
-                       (const typename C::elem*)cur, L.N, L.plane, L.d, partials);
+                       (const typename C::elem*)cur, L.N, L.nx, L.px, L.plane, L.d, partials);
     return hipGetLastError();
   });
   if (err != hipSuccess) return err;

@@ -129,10 +129,15 @@ int make_layout(const maclab_config* c, Layout* L, std::string* why) {
   L->ny = c->n[1];
   L->nz = c->n[2];
   L->N = N;
+  // D2Q9 rows start on 128-byte boundaries: the fast D2Q9 kernel moves rows
+  // segment by segment, and rows that straddle cache lines cost it about a
+  // third of its rate. D3Q19 rows are not padded (the fast D3Q19 kernel takes
+  // nx in {64, 128, 256}, whose rows are aligned already).
+  L->px = d == 2 ? (int64_t)round_up((size_t)L->nx, (size_t)(128 / L->bytes)) : L->nx;
   // 256 elements past a multiple of 512: the field planes of a power-of-two
   // lattice then do not start at addresses that differ only in their high
   // bits, which costs about 2% in a 256^3 step
-  L->plane = (int64_t)round_up((size_t)N, 512) + 256;
+  L->plane = (int64_t)round_up((size_t)(L->px * L->ny * L->nz), 512) + 256;
   L->state_bytes = (size_t)(d + 1) * (size_t)L->plane * (size_t)L->bytes;
   L->partial_bytes = round_up(sizeof(double) * (kDiagBlocks + 1) * kDiagValues, kAlign);
   L->staging_bytes = std::min(kStagingMax, round_up(sizeof(double) * (size_t)N, kAlign));
@@ -147,6 +152,7 @@ StepParams make_params(const maclab_t h) {
   p.nx = h->L.nx;
   p.ny = h->L.ny;
   p.nz = h->L.nz;
+  p.px = h->L.px;
   p.plane = h->L.plane;
   for (int ax = 0; ax < 3; ++ax) p.fixed[ax] = h->fv.kind[2 * ax] == MACLAB_BC_FIXED;
   p.rho_ref = h->cfg.rho_ref;
@@ -332,13 +338,13 @@ int maclab_set_fields(maclab_t h, const double* rho, const double* u, int on_dev
   for (int f = 0; f <= L.d; ++f) {
     const double* src = f == 0 ? rho : u + (size_t)(f - 1) * (size_t)L.N;
     if (on_device) {
-      HIP_TRY(h, launch_encode(L, plane_ptr(h, h->cur, f), src, L.N, offsets[f], muls[f], f, h->stream));
+      HIP_TRY(h, launch_encode(L, plane_ptr(h, h->cur, f), src, 0, L.N, offsets[f], muls[f], f, h->stream));
     } else {
       const int64_t chunk = (int64_t)(L.staging_bytes / sizeof(double));
       for (int64_t off = 0; off < L.N; off += chunk) {
         const int64_t cnt = std::min(chunk, L.N - off);
         HIP_TRY(h, hipMemcpyAsync(h->staging, src + off, sizeof(double) * cnt, hipMemcpyHostToDevice, h->stream));
-        HIP_TRY(h, launch_encode(L, plane_ptr(h, h->cur, f) + (size_t)off * L.bytes, (const double*)h->staging,
+        HIP_TRY(h, launch_encode(L, plane_ptr(h, h->cur, f), (const double*)h->staging, off,
                                  cnt, offsets[f], muls[f], f, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));  // staging is reused
       }
@@ -448,12 +454,12 @@ int maclab_get_fields(maclab_t h, double* rho, double* u, int on_device) {
   for (int f = 0; f <= L.d; ++f) {
     double* dst = f == 0 ? rho : u + (size_t)(f - 1) * (size_t)L.N;
     if (on_device) {
-      HIP_TRY(h, launch_decode(L, dst, plane_ptr(h, h->cur, f), L.N, offsets[f], muls[f], f, h->stream));
+      HIP_TRY(h, launch_decode(L, dst, plane_ptr(h, h->cur, f), 0, L.N, offsets[f], muls[f], f, h->stream));
     } else {
       const int64_t chunk = (int64_t)(L.staging_bytes / sizeof(double));
       for (int64_t off = 0; off < L.N; off += chunk) {
         const int64_t cnt = std::min(chunk, L.N - off);
-        HIP_TRY(h, launch_decode(L, (double*)h->staging, plane_ptr(h, h->cur, f) + (size_t)off * L.bytes, cnt,
+        HIP_TRY(h, launch_decode(L, (double*)h->staging, plane_ptr(h, h->cur, f), off, cnt,
                                  offsets[f], muls[f], f, h->stream));
         HIP_TRY(h, hipMemcpyAsync(dst + off, h->staging, sizeof(double) * cnt, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -794,7 +800,6 @@ struct maclab_batch_s {
   int64_t max_items = 0;
   int kx = 1, rows = 16;
   int nitems = 0;
-  int nvec = 0;                  // the first nvec items belong to lattices with aligned rows
   bool uploaded = false;
   int up_kx = 0, up_rows = 0;
   std::vector<Lattice2D> table_host;
@@ -904,10 +909,9 @@ int batch_plan(maclab_batch_t b, int kx, int rows, std::vector<Lattice2D>* table
     Lattice2D& t = (*table)[i];
     t.nx = (int)h->L.nx;
     t.ny = (int)h->L.ny;
-    t.pitch = t.nx;
+    t.pitch = (int)h->L.px;
     t.xper = !p.fixed[0];
     t.yper = !p.fixed[1];
-    t.aligned = (t.nx % kx) == 0;
     t.gx = p.g[0];
     t.gy = p.g[1];
     t.base = b->base[i];
@@ -921,12 +925,8 @@ int batch_plan(maclab_batch_t b, int kx, int rows, std::vector<Lattice2D>* table
     }
   }
   if ((int64_t)items->size() > b->max_items) return bfail(b, MACLAB_EINVAL, "too many work items for the workspace");
-  // items of lattices with aligned rows first (they run the vector-access
-  // kernel, the others a second launch); in each group the largest items
-  // first, so the tail of a launch is made of small ones
+  // the largest items first, so the tail of a launch is made of small ones
   std::stable_sort(items->begin(), items->end(), [&](const int4& a, const int4& c) {
-    const int va = (*table)[a.x].aligned, vc = (*table)[c.x].aligned;
-    if (va != vc) return va > vc;
     const int64_t wa = std::min(64 * kx, (*table)[a.x].nx - a.y), wc = std::min(64 * kx, (*table)[c.x].nx - c.y);
     return (int64_t)(a.w - a.z) * wa > (int64_t)(c.w - c.z) * wc;
   });
@@ -942,7 +942,7 @@ void drop_graph(maclab_batch_t b) {
 
 bool same_lattice(const Lattice2D& a, const Lattice2D& c) {
   return a.nx == c.nx && a.ny == c.ny && a.pitch == c.pitch && a.xper == c.xper && a.yper == c.yper &&
-         a.aligned == c.aligned && a.gx == c.gx && a.gy == c.gy && a.base == c.base && a.plane == c.plane;
+         a.gx == c.gx && a.gy == c.gy && a.base == c.base && a.plane == c.plane;
 }
 
 // Makes the device tables match the current tiling, faces and forces.
@@ -964,8 +964,6 @@ int batch_sync(maclab_batch_t b) {
                                hipMemcpyHostToDevice, b->stream));
   BHIP_TRY(b, hipStreamSynchronize(b->stream));  // the host copies may change before the next sync
   b->nitems = (int)b->items_host.size();
-  b->nvec = 0;
-  while (b->nvec < b->nitems && b->table_host[b->items_host[b->nvec].x].aligned) ++b->nvec;
   b->uploaded = true;
   b->up_kx = b->kx;
   b->up_rows = b->rows;
@@ -988,10 +986,8 @@ void batch_advance(maclab_batch_t b, int64_t n) {
 
 int batch_launch(maclab_batch_t b, hipStream_t s, int cur, int64_t step) {
   const uint32_t key = sr_key(b->seed, (uint64_t)step);
-  BHIP_TRY(b, launch_step_fast2d_items(b->precision, b->kx, true, b->state[cur], b->state[cur ^ 1], b->table,
-                                       b->items, b->nvec, b->rho_ref, key, s));
-  BHIP_TRY(b, launch_step_fast2d_items(b->precision, b->kx, false, b->state[cur], b->state[cur ^ 1], b->table,
-                                       b->items + b->nvec, b->nitems - b->nvec, b->rho_ref, key, s));
+  BHIP_TRY(b, launch_step_fast2d_items(b->precision, b->kx, b->state[cur], b->state[cur ^ 1], b->table, b->items,
+                                       b->nitems, b->rho_ref, key, s));
   return MACLAB_OK;
 }
 

@@ -398,6 +398,8 @@ FAST2D = [
     ("walled_300x77", 300, 77, True, (0.0, 0.0)),
     # periodic in both axes, width a multiple of 128, with a body force
     ("periodic_256x50", 256, 50, False, (0.2, -0.1)),
+    # walled, odd width: at W = 2 the last lane's second node is row padding
+    ("walled_131x40", 131, 40, True, (0.0, 0.0)),
 ]
 
 
@@ -432,6 +434,29 @@ def test_fast2d_every_tiling_is_bitwise_identical(name, nx, ny, walled, G, preci
                 assert rel_l2(u, ou) < TOL[precision] and rel_l2(rho, orho) < TOL[precision]
             else:
                 assert torch.equal(st, ref), (W, nb)
+
+
+@pytest.mark.parametrize("precision,elem", [("fp64", 8), ("fp32", 4), ("s16", 2)])
+def test_d2q9_rows_are_padded_and_the_padding_stays_zero(precision, elem):
+    """D2Q9 rows start on 128-byte boundaries (row pitch = nx rounded up to
+    128 bytes); steps never write the row padding of the library's buffers."""
+    nx, ny = 131, 40
+    px = -(-nx * elem // 128) * 128 // elem
+    plane = -(-px * ny // 512) * 512 + 256
+    case = _fast2d_case(nx, ny, True, (0.0, 0.0))
+    sim = make_sim(case, precision, seed=4)
+    assert sim.state_bytes() == 3 * plane * elem
+    for W in (1, 2):
+        sim.set_tiling(W=W, nzb=5, kernel="fast2d")
+        sim.step(3)
+    st = sim.save_state().cpu().numpy().view(np.uint8).reshape(3, plane * elem)
+    for f in range(3):
+        rows = st[f, :px * ny * elem].reshape(ny, px * elem)
+        assert not rows[:, nx * elem:].any(), f
+        assert not st[f, px * ny * elem:].any(), f
+    rho, u = sim.fields()
+    orho, ou = oracle.run(to_problem(case), case.rho, case.u, 6)
+    assert rel_l2(u, ou) < TOL[precision] and rel_l2(rho, orho) < TOL[precision]
 
 
 def test_fast2d_is_the_default_for_cavities():
