@@ -249,6 +249,68 @@ def test_full_size_step_on_sampled_nodes(name, mk, precision, tol):
         assert rel_l2(du_g, du_o) < (1e-9 if precision == "fp64" else 1e-3)
 
 
+@pytest.mark.slow
+def test_lattice_beyond_2_to_32_nodes():
+    """A 1630^3 lid-driven cube in S16 (4.33e9 nodes: more than 2^32, so more
+    than one grid dimension of work-items and 32-bit element offsets can
+    span). One step from rest, then sampled nodes of the native state: those
+    beside the lid equal the oracle's step on a 7^3 cube with the same dx, nu
+    and lid (a step reads only the neighbours), to the binary16 rounding of
+    the result; nodes away from the lid stay exactly at rest."""
+    need = 120 << 30
+    if torch.cuda.get_device_properties(0).total_memory < need:
+        pytest.skip("needs about 110 GB of device memory")
+    n, U, Re = 1630, 0.1, 400.0
+    dx, nu = 1.0 / (n - 1), U / Re  # the lid-driven cube of workloads.cavity_3d, without its host fields
+    m = 7
+    small = workloads.cavity_3d(n=m, Re=Re, U=U)
+    print(f"[large] {n}^3 s16: {n ** 3} nodes", flush=True)
+    sim = Simulation(19, (n, n, n), dx, nu, precision="s16", seed=3)
+    for face, (rb, ub) in small.fixed.items():
+        sim.set_bc(face, rb, ub)
+    e = sim.params()["e"]
+    sim.step(1)
+    st = sim.save_state()
+    plane = sim.state_bytes() // (4 * 2)  # four binary16 planes
+    assert plane >= n ** 3 > 2 ** 32
+    # the lid as stored (round to nearest of 2^6 U / e in binary16), for the oracle
+    lid16 = np.float16(np.float32(U / e) * np.float32(64.0))
+    U_s = float(lid16) / 64.0 * e
+    small.dx, small.nu = dx, nu
+    small.fixed["zhi"] = (1.0, (U_s, 0.0, 0.0))
+    orho, ou = oracle.run(to_problem(small), small.rho, small.u, 1)
+    h = n // 2
+    # (i, j, k) in the big cube -> (i, j, k) in the small one
+    near = [((1, 1, n - 2), (1, 1, m - 2)), ((h, h, n - 2), (3, 3, m - 2)), ((n - 2, h, n - 2), (m - 2, 3, m - 2)),
+            ((h, 1, n - 2), (3, 1, m - 2)), ((h, n - 2, n - 2), (3, m - 2, m - 2))]
+    rest = [(h, h, h), (1, 1, 1), (n - 2, n - 2, 1), (h, h, n - 3), (1, h, n - 4)]
+    lid = [(h, h, n - 1)]
+    pts = [b for b, _ in near] + rest + lid
+    node = torch.tensor([i + n * (j + n * k) for i, j, k in pts], dtype=torch.int64, device=st.device)
+    vals = []
+    for f in range(4):
+        off = 2 * (f * plane + node)
+        lo = st[off].to(torch.int32).cpu().numpy()
+        hi = st[off + 1].to(torch.int32).cpu().numpy()
+        vals.append((lo | (hi << 8)).astype(np.uint16).view(np.float16).astype(np.float64))
+    drho = vals[0] / 1024.0
+    ut = np.stack(vals[1:]) / 64.0
+    dr_scale = max(abs(orho[k, j, i] - 1.0) for _, (i, j, k) in near)
+    for q, (_, (i, j, k)) in enumerate(near):
+        want_u = ou[:, k, j, i] / e
+        want_dr = orho[k, j, i] - 1.0
+        # one binary16 rounding of the scaled result (under 2^-10 relative)
+        # plus FP32 arithmetic (the density deviation sums links about 25
+        # times larger than itself)
+        tol_u = 1.05 * 2.0 ** -10 * np.abs(want_u) + 1e-5 * np.abs(want_u).max() + 2.0 ** -30
+        assert np.all(np.abs(ut[:, q] - want_u) <= tol_u), (q, ut[:, q], want_u)
+        assert abs(drho[q] - want_dr) <= 1.05 * 2.0 ** -10 * abs(want_dr) + 1e-5 * dr_scale, (q, drho[q], want_dr)
+        assert np.abs(want_u).max() > 1e-4  # the lid reached this node
+    r0 = len(near)
+    assert np.all(drho[r0:r0 + len(rest)] == 0.0) and np.all(ut[:, r0:r0 + len(rest)] == 0.0)
+    assert ut[0, -1] == float(lid16) / 64.0 and drho[-1] == 0.0
+
+
 # --------------------------------------------- shapes taken by the fast path
 # D3Q19 with nx in {64, 128, 256} runs the wavefront-per-row kernel; these
 # cases cover its ragged y/z tiles, every boundary combination, tiny periodic
