@@ -139,8 +139,9 @@ int maclab_params(maclab_t h, double out[6]);
 
 /* Native state: the d+1 stored planes of the current step in storage format,
  * maclab_state_bytes(h) bytes. In a plane, node (i, j, k) sits at element
- * i + px (j + ny k): px = nx for D3Q19, and for D2Q9 nx rounded up to a
- * multiple of 128 bytes (so every row starts on a 128-byte boundary). The
+ * i + px (j + ny k): for D2Q9 px is nx rounded up to a multiple of 128 bytes
+ * (so every row starts on a 128-byte boundary); for D3Q19 it is the next of
+ * 64, 128, 256 when that is at most nx + nx/8, else nx. The
  * plane stride is px ny nz rounded up to 512, plus 256 elements. The library
  * never reads the padding (row ends and plane ends) and keeps it zero in its
  * own buffers. save copies the state to caller device memory; load

@@ -32,6 +32,7 @@ struct Fast3DParams {
   int ylo, nyo;            // first output row, number of output rows
   int zlo, nzo;            // first output plane, number of output planes
   int yper, zper, xwall;
+  int nxd;                 // nodes per row (the row pitch is 64 KX, nxd < 64 KX only with fixed x faces)
   int nyb, nzb, nblocks;   // workgroups along y and z, total
   int64_t plane;           // elements per field plane
   float rho_ref;
@@ -409,8 +410,10 @@ __device__ __forceinline__ E pick_bits(bool c, E a, E b) {
 // dropped. With the same sequence of memory operations on every path the
 // compiler's wait for a plane's loads lets the previous plane's stores stay in
 // flight. Wall nodes of a stored row are written back with the raw values of
-// the source row of the same plane, loaded one step before.
-template <class C, int KX, int W, int PF>
+// the source row of the same plane, loaded one step before. PADX: the rows
+// hold fewer than 64 KX nodes (fixed x faces); the lanes past the last node
+// read the row padding and keep it, like the walls, from the raw row.
+template <class C, int KX, int W, int PF, bool PADX>
 __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C::elem* __restrict__ src,
                                                                typename C::elem* __restrict__ dst, Fast3DParams p) {
   using E = typename C::elem;
@@ -475,8 +478,10 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
   };
   const bool wall_lane = p.xwall && (lane == 0 || lane == 63);
   // raw wall elements (element 0 of lane 0, element KX-1 of lane 63) of the
-  // row being pushed and of the row pushed one step before
+  // row being pushed and of the row pushed one step before; with PADX the
+  // whole raw rows
   E wcur[4], wprev[4];
+  V rcur[4], rprev[4];
 
   // One source plane: push its links, exchange the c_y = +-1 links through
   // LDS, then finalise destination plane zs-1 (STORE) or issue the same stores
@@ -498,8 +503,13 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
     }
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      wprev[f] = wcur[f];
-      wcur[f] = pick_bits(lane == 0, b.f[f].v[0], b.f[f].v[KX - 1]);
+      if constexpr (PADX) {
+        rprev[f] = rcur[f];
+        rcur[f] = b.f[f];
+      } else {
+        wprev[f] = wcur[f];
+        wcur[f] = pick_bits(lane == 0, b.f[f].v[0], b.f[f].v[KX - 1]);
+      }
     }
     if (mode == 0)
       push_row<C, KX, 0>(dr, ux, uy, uz, p.rho_ref, am, ac, ap, up, dn, lane);
@@ -517,9 +527,19 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
       // rounding bits of the row's nodes: one hash of the lane's first node,
       // spread to its KX nodes by distinct odd constants
       uint32_t hb = 0;
-      if constexpr (needs_rng<C>::value) hb = sr_node_bits(p.sr_key, nx * ((int64_t)yrow + (int64_t)p.ny * zwrap(zd)) + xbase);
+      if constexpr (needs_rng<C>::value)
+        hb = sr_node_bits(p.sr_key, (int64_t)p.nxd * ((int64_t)yrow + (int64_t)p.ny * zwrap(zd)) + xbase);
       finalize_row<C, KX>(am, p.rho_ref, p.g36x, p.g36y, p.g36z, hb, o);
-      if (wall_lane) {
+      if constexpr (PADX) {
+#pragma unroll
+        for (int e = 0; e < KX; ++e) {
+          const int x = xbase + e;
+          if (x == 0 || x >= p.nxd - 1) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) o[f].v[e] = rprev[f].v[e];
+          }
+        }
+      } else if (wall_lane) {
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           if (lane == 0)
@@ -550,7 +570,10 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
   if constexpr (PF == 2) load_plane(z0, true, b1);
   RawRow<C, KX>& c1 = PF == 2 ? b1 : b0;
 #pragma unroll
-  for (int f = 0; f < 4; ++f) wcur[f] = E{};
+  for (int f = 0; f < 4; ++f) {
+    wcur[f] = E{};
+    rcur[f] = V{};
+  }
   source_plane(NoStore{}, z0 - 1, a0, a1, a2, b0, 0);
   source_plane(NoStore{}, z0, a1, a2, a0, c1, 1);
   for (int zs = z0 + 1; zs <= z1; zs += 6) {
@@ -693,11 +716,13 @@ static const int kFastW[] = {4, 6, 8, 10, 12};
 bool fast_step_supported(const Layout& L, const StepParams& p) {
   if (L.q != 19) return false;
   if (L.precision != MACLAB_FP32 && L.precision != MACLAB_HILO && L.precision != MACLAB_S16) return false;
-  if (L.nx != 64 && L.nx != 128 && L.nx != 256) return false;
-  if (L.px != L.nx) return false;  // rows are exactly one wavefront's nodes
+  // one wavefront per row of 64, 128 or 256 nodes; a shorter row (padded to
+  // that pitch) only between fixed x faces, since a periodic row wraps through
+  // the wavefront's lanes
+  if (L.px != 64 && L.px != 128 && L.px != 256) return false;
+  if (L.px != L.nx && !p.fixed[0]) return false;
   if (L.ny < 3 || L.nz < 3) return false;
   if (L.plane * L.bytes >= (int64_t(1) << 31)) return false;  // buffer offsets are 31-bit
-  (void)p;
   return true;
 }
 
@@ -722,6 +747,7 @@ bool fast_shape_valid(const Layout& L, const StepParams& p, const FastShape& sh)
   if (!w_ok || (sh.pf != 1 && sh.pf != 2) || sh.nyb < 1 || sh.nzb < 1 || sh.nyb > nyo || sh.nzb > nzo)
     return false;
   if (sh.pf == 2 && sh.W > 10) return false;  // the two-plane buffer would not fit in registers
+  if (sh.pf == 2 && L.px != L.nx) return false;  // padded rows: one-plane prefetch only
   return (nyo + sh.nyb - 1) / sh.nyb <= sh.W;
 }
 
@@ -774,23 +800,24 @@ int fast_candidates(const Layout& L, const StepParams& p, int cus, FastShape* ou
   return n;
 }
 
-template <class C, int KX, int W, int PF>
+template <class C, int KX, int W, int PF, bool PADX>
 static hipError_t launch_fast_w(const void* src, void* dst, const Fast3DParams& fp, hipStream_t s) {
   using E = typename C::elem;
   const dim3 block(64, W + 2, 1);
-  hipLaunchKernelGGL((step_d3q19_fast<C, KX, W, PF>), dim3(fp.nblocks), block, 0, s, (const E*)src, (E*)dst, fp);
+  hipLaunchKernelGGL((step_d3q19_fast<C, KX, W, PF, PADX>), dim3(fp.nblocks), block, 0, s, (const E*)src, (E*)dst,
+                     fp);
   return hipGetLastError();
 }
 
-template <class C, int KX, int PF>
+template <class C, int KX, int PF, bool PADX>
 static hipError_t launch_fast_pf(int W, const void* src, void* dst, const Fast3DParams& fp, hipStream_t s) {
   switch (W) {
-    case 4: return launch_fast_w<C, KX, 4, PF>(src, dst, fp, s);
-    case 6: return launch_fast_w<C, KX, 6, PF>(src, dst, fp, s);
-    case 8: return launch_fast_w<C, KX, 8, PF>(src, dst, fp, s);
-    case 10: return launch_fast_w<C, KX, 10, PF>(src, dst, fp, s);
+    case 4: return launch_fast_w<C, KX, 4, PF, PADX>(src, dst, fp, s);
+    case 6: return launch_fast_w<C, KX, 6, PF, PADX>(src, dst, fp, s);
+    case 8: return launch_fast_w<C, KX, 8, PF, PADX>(src, dst, fp, s);
+    case 10: return launch_fast_w<C, KX, 10, PF, PADX>(src, dst, fp, s);
     case 12:
-      if constexpr (PF == 1) return launch_fast_w<C, KX, 12, PF>(src, dst, fp, s);
+      if constexpr (PF == 1) return launch_fast_w<C, KX, 12, PF, PADX>(src, dst, fp, s);
       break;
   }
   return hipErrorInvalidValue;
@@ -819,13 +846,19 @@ static hipError_t launch_fast_kx(const FastShape& sh, const void* src, void* dst
     }
     return hipErrorInvalidValue;
   }
-  return sh.pf == 2 ? launch_fast_pf<C, KX, 2>(sh.W, src, dst, fp, s) : launch_fast_pf<C, KX, 1>(sh.W, src, dst, fp, s);
+  if (fp.nxd != 64 * KX) {
+    // padded rows: the two-plane prefetch variant is not built for them
+    if (sh.pf != 1) return hipErrorInvalidValue;
+    return launch_fast_pf<C, KX, 1, true>(sh.W, src, dst, fp, s);
+  }
+  return sh.pf == 2 ? launch_fast_pf<C, KX, 2, false>(sh.W, src, dst, fp, s)
+                    : launch_fast_pf<C, KX, 1, false>(sh.W, src, dst, fp, s);
 }
 
 template <class C>
 static hipError_t launch_fast_codec(const Layout& L, const FastShape& sh, const void* src, void* dst,
                                     const Fast3DParams& fp, hipStream_t s) {
-  switch (L.nx) {
+  switch (L.px) {
     case 64: return launch_fast_kx<C, 1>(sh, src, dst, fp, s);
     case 128: return launch_fast_kx<C, 2>(sh, src, dst, fp, s);
     case 256: return launch_fast_kx<C, 4>(sh, src, dst, fp, s);
@@ -842,6 +875,7 @@ hipError_t launch_step_fast(const Layout& L, const void* src, void* dst, const S
   fp.yper = !p.fixed[1];
   fp.zper = !p.fixed[2];
   fp.xwall = p.fixed[0];
+  fp.nxd = (int)L.nx;
   output_ranges(L, p, &fp.nyo, &fp.nzo);
   fp.ylo = fp.yper ? 0 : 1;
   fp.zlo = fp.zper ? 0 : 1;

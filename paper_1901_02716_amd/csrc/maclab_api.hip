@@ -131,9 +131,19 @@ int make_layout(const maclab_config* c, Layout* L, std::string* why) {
   L->N = N;
   // D2Q9 rows start on 128-byte boundaries: the fast D2Q9 kernel moves rows
   // segment by segment, and rows that straddle cache lines cost it about a
-  // third of its rate. D3Q19 rows are not padded (the fast D3Q19 kernel takes
-  // nx in {64, 128, 256}, whose rows are aligned already).
-  L->px = d == 2 ? (int64_t)round_up((size_t)L->nx, (size_t)(128 / L->bytes)) : L->nx;
+  // third of its rate. A D3Q19 row is padded to the next row width of the
+  // fast D3Q19 kernel (64, 128 or 256 nodes, one wavefront per row) when that
+  // adds at most an eighth, so that lattices such as 251^3 run on it.
+  if (d == 2) {
+    L->px = (int64_t)round_up((size_t)L->nx, (size_t)(128 / L->bytes));
+  } else {
+    L->px = L->nx;
+    for (int64_t w : {64, 128, 256})
+      if (w >= L->nx) {
+        if (8 * w <= 9 * L->nx) L->px = w;
+        break;
+      }
+  }
   // 256 elements past a multiple of 512: the field planes of a power-of-two
   // lattice then do not start at addresses that differ only in their high
   // bits, which costs about 2% in a 256^3 step

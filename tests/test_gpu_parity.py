@@ -321,6 +321,10 @@ FAST = [
     ("wx_py_wz_256x13x9", 256, (13, 9), ("x", "z"), (0.0, 0.2, 0.0)),
     ("periodic_64x3x3", 64, (3, 3), (), (0.1, 0.1, 0.1)),
     ("periodic_128x7x5", 128, (7, 5), (), (0.0, 0.0, 0.0)),
+    # rows padded to the kernel's row width (fixed x faces): 251 -> 256, 121 -> 128, 60 -> 64
+    ("walled_251x11x9", 251, (11, 9), ("x", "y", "z"), (0.0, 0.0, 0.0)),
+    ("wx_py_pz_121x13x7", 121, (13, 7), ("x",), (0.0, 0.3, -0.1)),
+    ("walled_60x9x8", 60, (9, 8), ("x", "y", "z"), (0.0, 0.0, 0.0)),
 ]
 
 
@@ -413,6 +417,52 @@ def test_fast_path_every_tiling_is_bitwise_identical(name, nx, nyz, walls, G):
             assert rel_l2(u, ou) < 1e-5 and rel_l2(rho, orho) < 1e-5
         else:
             assert torch.equal(st, ref), (W, nyb, nzb, pf, kern)
+
+
+@pytest.mark.parametrize("name,nx,nyz,walls,G", FAST[5:], ids=[f[0] for f in FAST[5:]])
+def test_fast_path_padded_rows(name, nx, nyz, walls, G):
+    """Rows shorter than the kernel's row width (padded to it): the exchange
+    kernel runs, every tiling gives the same bits, they match the oracle, and
+    the row padding stays zero."""
+    case = _fast_case(nx, nyz, walls, G)
+    px = next(w for w in (64, 128, 256) if w >= nx)
+    nyo = nyz[0] - 2 if "y" in walls else nyz[0]
+    nzo = nyz[1] - 2 if "z" in walls else nyz[1]
+    ref = None
+    for W, nyb, nzb, pf, kern in [t for t in _tilings(nyo, nzo) if t[3] == 1]:
+        sim = make_sim(case, "fp32")
+        if ref is None:
+            assert sim.tiling()["kernel"] == "exchange"
+            assert sim.state_bytes() == 4 * 4 * (-(-px * nyz[0] * nyz[1] // 512) * 512 + 256)
+        sim.set_tiling(W, nyb, nzb, pf, kern)
+        sim.step(6)
+        st = sim.save_state()
+        if ref is None:
+            ref = st.clone()
+            rho, u = sim.fields()
+            orho, ou = oracle.run(to_problem(case), case.rho, case.u, 6)
+            assert rel_l2(u, ou) < 1e-5 and rel_l2(rho, orho) < 1e-5
+            plane = st.numel() // 16
+            f32 = st.cpu().numpy().view(np.float32).reshape(4, plane)
+            rows = f32[:, :px * nyz[0] * nyz[1]].reshape(4, -1, px)
+            assert not rows[:, :, nx:].any()
+        else:
+            assert torch.equal(st, ref), (W, nyb, nzb, pf, kern)
+    with pytest.raises(MaclabError):
+        make_sim(case, "fp32").set_tiling(8, -(-nyo // 8), 1, 2, "exchange")  # no two-plane prefetch here
+
+
+def test_padded_periodic_rows_take_the_general_kernel():
+    """A D3Q19 row padded to 64 nodes but periodic in x cannot wrap through
+    a wavefront: the general kernel runs it (on the padded layout)."""
+    case = workloads.random_field(19, (60, 6, 5), seed=9, amp=0.03)
+    sim = make_sim(case, "fp32")
+    assert sim.tiling()["kernel"] == "general"
+    assert sim.state_bytes() == 4 * 4 * (-(-64 * 30 // 512) * 512 + 256)
+    sim.step(5)
+    rho, u = sim.fields()
+    orho, ou = oracle.run(to_problem(case), case.rho, case.u, 5)
+    assert rel_l2(u, ou) < 1e-5 and rel_l2(rho, orho) < 1e-5
 
 
 def test_invalid_tiling_rejected():
