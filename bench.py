@@ -15,7 +15,8 @@ Output: one JSON line with
   - `copy_ceiling`: the library's streaming copy of the same state buffer
     back and forth, the memory rate a step can reach on this device;
   - `cpu_baseline`: the FP64 CPU oracle timed on a bounded sample of the
-    same workload;
+    same workload, one single-threaded oracle process per host core (at
+    most 16), each on its own copy;
   - `variants` (S16, HILO), `adjoint` (the 512^2 D2Q9 reverse mode against
     the forward), `batch` (512 D2Q9 cavities in one launch per step against
     one launch per cavity), `launch_bound` (a 64^2 lattice) and
@@ -296,18 +297,53 @@ def time_steady(tol: float = 1e-10, check_every: int = 5000):
             "wall_s": round(wall, 3), "mlups": round(lu / wall / 1e6, 1)}
 
 
-def cpu_baseline(case, steps: int):
-    """The FP64 oracle on `steps` steps of the same lattice, one thread."""
+def _oracle_steps(workload: str, steps: int) -> float:
+    """Seconds the FP64 oracle (single-threaded C) takes for `steps` steps of
+    a workload lattice, from its initial state."""
     import oracle
 
+    case = make_case(WORKLOADS[workload])
     p = oracle.Problem(case.q, case.n, case.dx, case.nu)
     for face, (rb, ub) in case.fixed.items():
         p.set_fixed(face, rb, ub)
-    oracle.build()
     t0 = time.perf_counter()
     oracle.run(p, case.rho, case.u, steps)
-    dt = time.perf_counter() - t0
-    return updated_nodes(case) * steps / dt / 1e6, dt
+    return time.perf_counter() - t0
+
+
+def host_cores() -> int:
+    """Host cores to run the oracle on: those this process may use, at most
+    16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(workload: str, steps: int, procs: int):
+    """The FP64 oracle on `steps` steps of the workload lattice, as `procs`
+    independent processes at once (one per host core, each on its own copy).
+    They are child processes that import only the oracle and the input
+    generators, so none of them touches the GPU. Returns the aggregate MLUPS,
+    the slowest process's seconds and the per-process seconds."""
+    import subprocess
+
+    import oracle
+
+    oracle.build()  # once, before the workers load it
+    code = f"import sys; sys.path.insert(0, {ROOT!r}); import bench; print(bench._oracle_steps({workload!r}, {steps}))"
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    workers = [subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE, text=True, env=env)
+               for _ in range(procs)]
+    secs = []
+    for w in workers:
+        out, _ = w.communicate()
+        if w.returncode != 0:
+            raise RuntimeError(f"oracle worker failed with status {w.returncode}")
+        secs.append(float(out.strip().splitlines()[-1]))
+    lu = updated_nodes(make_case(WORKLOADS[workload])) * steps
+    return procs * lu / max(secs) / 1e6, max(secs), secs
 
 
 def load_traffic(workload: str, precision: str):
@@ -334,6 +370,7 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32", choices=sorted(BYTES))
     ap.add_argument("--variants", default="s16,hilo", help="extra storage variants to time ('' for none)")
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes of the CPU baseline (0: host cores, at most 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-steady", action="store_true", help="skip the steady-state run of the 2-D cavity")
     ap.add_argument("--no-autotune", action="store_true", help="use the default tiling")
@@ -388,10 +425,13 @@ def main(argv=None):
 
     cpu = None
     if not args.no_cpu_baseline:
-        cm, cdt = cpu_baseline(case, args.cpu_steps)
-        cpu = {"value": round(cm, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-               "sample": f"{args.cpu_steps} FP64 steps of the same {wl['desc']} lattice "
-                         f"({args.cpu_steps * lu} lattice updates, {cdt:.1f} s, single thread)"}
+        procs = args.cpu_procs or host_cores()
+        cm, cdt, csecs = cpu_baseline(args.workload, args.cpu_steps, procs)
+        cpu = {"value": round(cm, 3), "unit": "MLUPS", "cores": procs, "kind": "oracle",
+               "sample": f"{args.cpu_steps} FP64 steps of the same {wl['desc']} lattice in each of {procs} "
+                         f"single-threaded oracle processes at once ({procs} x {args.cpu_steps * lu} lattice "
+                         f"updates; slowest {cdt:.1f} s, fastest {min(csecs):.1f} s; one process alone: "
+                         f"about {args.cpu_steps * lu / min(csecs) / 1e6:.2f} MLUPS)"}
 
     if args.profile_copy_mib > 0:
         n = args.profile_copy_mib << 20
