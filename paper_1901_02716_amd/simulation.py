@@ -18,6 +18,19 @@ _PRECISIONS = {"fp64": _lib.FP64, "fp32": _lib.FP32, "hilo": _lib.HILO, "s16": _
 _FACES = {"xlo": 0, "xhi": 1, "ylo": 2, "yhi": 3, "zlo": 4, "zhi": 5}
 
 
+def _device_ptr(t: torch.Tensor, nbytes: int, name: str) -> int:
+    """Address of a contiguous device tensor of at least `nbytes` bytes (the
+    library takes plain device pointers and cannot check them)."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a tensor in GPU memory")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    have = t.numel() * t.element_size()
+    if have < nbytes:
+        raise ValueError(f"{name} holds {have} bytes, needs {nbytes}")
+    return t.data_ptr()
+
+
 def _aligned_workspace(nbytes: int, device) -> tuple[torch.Tensor, int]:
     buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
     off = (-buf.data_ptr()) % 256
@@ -85,13 +98,15 @@ class Simulation:
         if on_dev:
             r = torch.as_tensor(rho).to(self.device, torch.float64).contiguous()
             v = torch.as_tensor(u).to(self.device, torch.float64).contiguous()
-            assert r.numel() == self.N and v.numel() == self.d * self.N
+            if r.numel() != self.N or v.numel() != self.d * self.N:
+                raise ValueError(f"rho needs {self.N} values and u {self.d * self.N}")
             _lib.check(self.lib.maclab_set_fields(self.h, r.data_ptr(), v.data_ptr(), 1), self.h)
             torch.cuda.current_stream(self.device).synchronize()
         else:
             r = np.ascontiguousarray(np.asarray(rho, dtype=np.float64).ravel())
             v = np.ascontiguousarray(np.asarray(u, dtype=np.float64).ravel())
-            assert r.size == self.N and v.size == self.d * self.N
+            if r.size != self.N or v.size != self.d * self.N:
+                raise ValueError(f"rho needs {self.N} values and u {self.d * self.N}")
             _lib.check(self.lib.maclab_set_fields(self.h, r.ctypes.data, v.ctypes.data, 0), self.h)
 
     # ------------------------------------------------------------ stepping
@@ -160,7 +175,9 @@ class Simulation:
     def step_external(self, src: torch.Tensor, dst: torch.Tensor, step_index: int) -> None:
         """One step from the native state in `src` to `dst` (device buffers of
         state_bytes()); the simulation's own state does not change."""
-        _lib.check(self.lib.maclab_step_external(self.h, src.data_ptr(), dst.data_ptr(), int(step_index)), self.h)
+        nb = self.state_bytes()
+        _lib.check(self.lib.maclab_step_external(self.h, _device_ptr(src, nb, "src"), _device_ptr(dst, nb, "dst"),
+                                                 int(step_index)), self.h)
 
     def residual(self) -> tuple[float, float, int]:
         """Change over the last step: (max |u(n) - u(n-1)|, max |rho(n) -
@@ -184,8 +201,7 @@ class Simulation:
         """Streaming device copy on the simulation's stream (calibration: the
         memory rate of a step without its arithmetic)."""
         n = src.numel() * src.element_size() if nbytes is None else int(nbytes)
-        assert n <= src.numel() * src.element_size() and n <= dst.numel() * dst.element_size()
-        _lib.check(self.lib.maclab_copy(self.h, src.data_ptr(), dst.data_ptr(), n), self.h)
+        _lib.check(self.lib.maclab_copy(self.h, _device_ptr(src, n, "src"), _device_ptr(dst, n, "dst"), n), self.h)
 
     def adjoint_bytes(self) -> int:
         return int(self.lib.maclab_adjoint_bytes(self.h))
@@ -200,16 +216,20 @@ class Simulation:
     def adjoint_seed(self, state_T: torch.Tensor, dLdu: torch.Tensor, adj: torch.Tensor) -> None:
         """Adjoint at the last step T from its native state and dL/du(T)."""
         g = dLdu.to(self.device, torch.float64).contiguous()
-        assert g.numel() == self.d * self.N
-        _lib.check(self.lib.maclab_adjoint_seed(self.h, state_T.data_ptr(), g.data_ptr(), adj.data_ptr()), self.h)
+        if g.numel() != self.d * self.N:
+            raise ValueError(f"dLdu needs {self.d * self.N} values")
+        _lib.check(self.lib.maclab_adjoint_seed(self.h, _device_ptr(state_T, self.state_bytes(), "state_T"),
+                                                g.data_ptr(), _device_ptr(adj, self.adjoint_bytes(), "adj")), self.h)
         self._keep = g  # alive until the stream has consumed it
 
     def adjoint_reset(self) -> None:
         _lib.check(self.lib.maclab_adjoint_reset(self.h), self.h)
 
     def adjoint_step(self, state_n, adj_np1, adj_n) -> None:
-        _lib.check(self.lib.maclab_adjoint_step(self.h, state_n.data_ptr(), adj_np1.data_ptr(),
-                                                adj_n.data_ptr()), self.h)
+        ab = self.adjoint_bytes()
+        _lib.check(self.lib.maclab_adjoint_step(self.h, _device_ptr(state_n, self.state_bytes(), "state_n"),
+                                                _device_ptr(adj_np1, ab, "adj_np1"), _device_ptr(adj_n, ab, "adj_n")),
+                   self.h)
 
     def adjoint_segment(self, ckpt, states, nsteps: int, step_index: int, adj, which: int) -> int:
         """Reverse sweep over steps step_index .. step_index+nsteps-1 from the
@@ -217,9 +237,11 @@ class Simulation:
         the adjoint at step_index+nsteps. Returns the index of the buffer that
         holds the adjoint at step_index."""
         w = ctypes.c_int(int(which))
-        sp = states.data_ptr() if states is not None else None
-        _lib.check(self.lib.maclab_adjoint_segment(self.h, ckpt.data_ptr(), sp, int(nsteps), int(step_index),
-                                                   adj[0].data_ptr(), adj[1].data_ptr(), ctypes.byref(w)), self.h)
+        sb, ab = self.state_bytes(), self.adjoint_bytes()
+        sp = _device_ptr(states, (int(nsteps) - 1) * sb, "states") if states is not None else None
+        _lib.check(self.lib.maclab_adjoint_segment(self.h, _device_ptr(ckpt, sb, "ckpt"), sp, int(nsteps),
+                                                   int(step_index), _device_ptr(adj[0], ab, "adj[0]"),
+                                                   _device_ptr(adj[1], ab, "adj[1]"), ctypes.byref(w)), self.h)
         return w.value
 
     def adjoint_result(self, state0: torch.Tensor, adj0: torch.Tensor, want_rho: bool = False):
@@ -229,7 +251,8 @@ class Simulation:
         gu = torch.empty((self.d,) + shape, dtype=torch.float64, device=self.device)
         gr = torch.empty(shape, dtype=torch.float64, device=self.device) if want_rho else None
         gG = np.zeros(3)
-        _lib.check(self.lib.maclab_adjoint_result(self.h, state0.data_ptr(), adj0.data_ptr(), gu.data_ptr(),
+        _lib.check(self.lib.maclab_adjoint_result(self.h, _device_ptr(state0, self.state_bytes(), "state0"),
+                                                  _device_ptr(adj0, self.adjoint_bytes(), "adj0"), gu.data_ptr(),
                                                   gr.data_ptr() if gr is not None else None,
                                                   gG.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self.h)
         return (gu, gG, gr) if want_rho else (gu, gG)
@@ -250,13 +273,11 @@ class Simulation:
     def save_state(self, out: torch.Tensor | None = None) -> torch.Tensor:
         if out is None:
             out = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
-        assert out.numel() * out.element_size() >= self.state_bytes()
-        _lib.check(self.lib.maclab_save_state(self.h, out.data_ptr()), self.h)
+        _lib.check(self.lib.maclab_save_state(self.h, _device_ptr(out, self.state_bytes(), "out")), self.h)
         return out
 
     def load_state(self, src: torch.Tensor) -> None:
-        assert src.numel() * src.element_size() >= self.state_bytes()
-        _lib.check(self.lib.maclab_load_state(self.h, src.data_ptr()), self.h)
+        _lib.check(self.lib.maclab_load_state(self.h, _device_ptr(src, self.state_bytes(), "src")), self.h)
 
     @classmethod
     def _view(cls, lib, h, lattice: int, n, precision: str, device, stream, owner) -> "Simulation":

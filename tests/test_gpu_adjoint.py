@@ -225,6 +225,27 @@ def test_step_external_matches_step():
     assert torch.equal(sim.save_state(), b)
 
 
+def test_binding_rejects_unusable_device_buffers():
+    """The library takes plain device pointers; the binding checks that a
+    buffer lives on the GPU, is contiguous and is large enough before any
+    kernel sees it."""
+    case, _ = _case(9, (40, 24, 1), True)
+    sim = _sim(case, "fp32")
+    s0 = sim.save_state()
+    good = torch.empty_like(s0)
+    with pytest.raises(ValueError, match="GPU memory"):
+        sim.step_external(s0, good.cpu(), 0)
+    with pytest.raises(ValueError, match="needs"):
+        sim.step_external(s0, good[: good.numel() // 2], 0)
+    with pytest.raises(ValueError, match="contiguous"):
+        sim.load_state(torch.empty(2 * s0.numel(), dtype=torch.uint8, device=s0.device)[::2])
+    adj = sim.new_adjoint()
+    with pytest.raises(ValueError, match="needs"):
+        sim.adjoint_step(s0, adj, adj[:16])
+    sim.step_external(s0, good, 0)  # the valid call still works
+    torch.cuda.synchronize()
+
+
 FD_FILE = os.path.join(HERE, "golden", "adjoint512_fd.json")
 
 
