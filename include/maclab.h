@@ -155,12 +155,13 @@ int maclab_load_state(maclab_t h, const void* src_device);
 
 /* Kernel and tiling of the step. out[5] = {kernel, W, nyb, nzb, pf}.
  *  kernel 0: general kernel (any shape and boundaries; no tiling).
- *  kernel 1: fast D3Q19, LDS exchange (x extent 64, 128 or 256; FP32
- *    arithmetic): one wavefront per x-row marches in z; workgroups of W
- *    output rows (W in {4,6,8,10,12}) plus two halo rows exchange the
- *    y-links through LDS; nyb x nzb workgroups with balanced (y, z) ranges;
- *    pf (1 or 2, 2 only with W <= 10) source planes loaded ahead. Needs
- *    ceil(rows / nyb) <= W.
+ *  kernel 1: fast D3Q19, LDS exchange (row pitch 64, 128 or 256: x extent
+ *    64, 128 or 256, or between fixed x faces an extent padded to one of
+ *    them; FP32 arithmetic): one wavefront per x-row marches in z;
+ *    workgroups of W output rows (W in {4,6,8,10,12}) plus two halo rows
+ *    exchange the y-links through LDS; nyb x nzb workgroups with balanced
+ *    (y, z) ranges; pf (1 or 2, 2 only with W <= 10 and unpadded rows)
+ *    source planes loaded ahead. Needs ceil(rows / nyb) <= W.
  *  kernel 2: fast D3Q19, independent wavefronts (x extent 64 only): each
  *    wavefront owns one row and one of nzb balanced z-chunks and evaluates
  *    the links of the neighbouring rows it needs itself (no LDS, no
