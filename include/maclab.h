@@ -179,9 +179,11 @@ int maclab_set_tiling(maclab_t h, int kernel, int W, int nyb, int nzb, int pf);
 
 /* Times the candidate tilings of this lattice (each launched `reps` times
  * from the current state into the spare buffer, so the simulation does not
- * advance) and keeps the fastest; *best_ms (may be NULL) receives its time
- * per step. The spare buffer then holds the state one step ahead, so until
- * the next step maclab_residual gives the change over that step. Synchronises. */
+ * advance; before each timed launch an untimed pass reads the spare buffer,
+ * so that the launch finds its source out of the caches, as a step does)
+ * and keeps the fastest; *best_ms (may be NULL) receives its time per step.
+ * The spare buffer then holds the state one step ahead, so until the next
+ * step maclab_residual gives the change over that step. Synchronises. */
 int maclab_autotune(maclab_t h, int reps, double* best_ms);
 
 /* Replaces the uniform body force G (physical units) for subsequent steps. */

@@ -251,37 +251,49 @@ struct BufIO;
 template <>
 struct BufIO<2> {
   using U = unsigned short;
-  __device__ static U load(buf_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0); }
+  template <int AUX>
+  __device__ static U load(buf_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, AUX); }
   template <int AUX>
   __device__ static void store(U v, buf_t r, int off) { __builtin_amdgcn_raw_buffer_store_b16(v, r, off, 0, AUX); }
 };
 template <>
 struct BufIO<4> {
   using U = unsigned int;
-  __device__ static U load(buf_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0); }
+  template <int AUX>
+  __device__ static U load(buf_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX); }
   template <int AUX>
   __device__ static void store(U v, buf_t r, int off) { __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, AUX); }
 };
 template <>
 struct BufIO<8> {
   typedef unsigned int U __attribute__((ext_vector_type(2)));
-  __device__ static U load(buf_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0); }
+  template <int AUX>
+  __device__ static U load(buf_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX); }
   template <int AUX>
   __device__ static void store(U v, buf_t r, int off) { __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, AUX); }
 };
 template <>
 struct BufIO<16> {
   typedef unsigned int U __attribute__((ext_vector_type(4)));
-  __device__ static U load(buf_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0); }
+  template <int AUX>
+  __device__ static U load(buf_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, AUX); }
   template <int AUX>
   __device__ static void store(U v, buf_t r, int off) { __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, AUX); }
 };
 
 // Loads / stores a trivially copyable V (2, 4, 8 or 16 bytes) at a byte offset;
 // AUX is the cache-policy word (2: non-temporal).
-template <class V>
+template <class V, int AUX = 0>
 __device__ __forceinline__ V buf_load(buf_t r, int off) {
-  return __builtin_bit_cast(V, BufIO<sizeof(V)>::load(r, off));
+  return __builtin_bit_cast(V, BufIO<sizeof(V)>::template load<AUX>(r, off));
+}
+// Bitwise or of two loaded values: of a load and an out-of-range load (which
+// reads zero), the loaded value.
+template <class V>
+__device__ __forceinline__ V buf_or(const V& a, const V& b) {
+  using U = typename BufIO<sizeof(V)>::U;
+  const U r = (U)(__builtin_bit_cast(U, a) | __builtin_bit_cast(U, b));
+  return __builtin_bit_cast(V, r);
 }
 template <class V, int AUX = 0>
 __device__ __forceinline__ void buf_store(const V& v, buf_t r, int off) {

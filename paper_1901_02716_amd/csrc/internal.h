@@ -62,6 +62,10 @@ hipError_t launch_residual(const Layout& L, const void* prev, const void* cur, d
                            hipStream_t s);
 // Streaming copy of `bytes` (a multiple of 16; 16-byte aligned, disjoint).
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+// Reads `bytes` (a multiple of 16, 16-byte aligned) with ordinary cached loads
+// and keeps nothing (`sink` is written only if the data hash equals `key`,
+// so the loads stay): it fills the caches with this buffer.
+hipError_t launch_touch(const void* buf, size_t bytes, uint32_t* sink, uint32_t key, hipStream_t s);
 hipError_t launch_diagnostics(const Layout& L, const void* state, double rho_ref, double e, double* partials,
                               double* result, hipStream_t s);
 

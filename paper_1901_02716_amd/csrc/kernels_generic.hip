@@ -356,15 +356,16 @@ hipError_t launch_diagnostics(const Layout& L, const void* state, double rho_ref
   return hipGetLastError();
 }
 
-// Streaming copy of n16 16-byte words: 16-byte loads and non-temporal 16-byte
-// stores, the store form of the step kernels. It moves the bytes of a step
-// with none of its arithmetic, so its rate is the memory rate a step can
-// reach.
+// Streaming copy of n16 16-byte words: non-temporal 16-byte loads and stores
+// (the fastest copy form measured on the device; the step kernels store this
+// way and load most rows this way). It moves the bytes of a step with none
+// of its arithmetic, so its rate is the memory rate a step can reach.
 __global__ void stream_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16) {
   typedef uint32_t w4 __attribute__((ext_vector_type(4)));
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
-    __builtin_nontemporal_store(__builtin_bit_cast(w4, src[i]), reinterpret_cast<w4*>(dst + i));
+    __builtin_nontemporal_store(__builtin_nontemporal_load(reinterpret_cast<const w4*>(src + i)),
+                                reinterpret_cast<w4*>(dst + i));
 }
 
 hipError_t launch_residual(const Layout& L, const void* prev, const void* cur, double* partials, double* result,
@@ -379,6 +380,25 @@ hipError_t launch_residual(const Layout& L, const void* prev, const void* cur, d
   });
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(residual_final_kernel, dim3(1), dim3(256), 0, s, partials, blocks, result);
+  return hipGetLastError();
+}
+
+__global__ void touch_kernel(const uint4* __restrict__ p, int64_t n16, uint32_t* __restrict__ sink, uint32_t key) {
+  uint32_t acc = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) {
+    const uint4 v = p[i];
+    acc ^= v.x ^ v.y ^ v.z ^ v.w;
+  }
+  if (acc == key) sink[0] = acc;
+}
+
+hipError_t launch_touch(const void* buf, size_t bytes, uint32_t* sink, uint32_t key, hipStream_t s) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 == 0) return hipSuccess;
+  const int64_t want = (n16 + 255) / 256;
+  const unsigned blocks = (unsigned)(want < 8192 ? want : 8192);
+  hipLaunchKernelGGL(touch_kernel, dim3(blocks), dim3(256), 0, s, (const uint4*)buf, n16, sink, key);
   return hipGetLastError();
 }
 
