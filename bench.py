@@ -458,8 +458,8 @@ def main(argv=None):
                    "bytes_per_lattice_update": b_lu, "tiling": info["tiling"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
-        "copy_ceiling": {"kernel": "maclab_copy: the state buffer copied back and forth (16-byte loads, "
-                                   "non-temporal 16-byte stores)",
+        "copy_ceiling": {"kernel": "maclab_copy: the state buffer copied back and forth (non-temporal "
+                                   "16-byte loads and stores)",
                          "bytes_per_copy": info["copy_bytes"], "ms_per_copy": round(info["copy_ms"], 5),
                          "gbs": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),
                          "step_frac_of_copy": round(achieved / copy_gbs, 4)},
