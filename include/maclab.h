@@ -277,7 +277,9 @@ int maclab_get_adjoint_tiling(maclab_t h, int out[3]);
  *  get_tiling:    out[3] = {kx, rows, work items}. set_tiling: kx in {1,2},
  *                 rows >= 4 (a periodic x extent must be a multiple of
  *                 64*kx). autotune: times every candidate (each launched
- *                 `reps` times into the spare buffers, so nothing advances),
+ *                 `reps` times into the spare buffers, so nothing advances;
+ *                 an untimed pass over the spare buffers before each timed
+ *                 launch leaves the source out of the caches, as in a step),
  *                 keeps the fastest; *best_ms (may be NULL) gets its time per
  *                 step. set_graph: steps per captured graph, even, 0 for none
  *                 (default 32). */
