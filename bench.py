@@ -49,11 +49,15 @@ BYTES = {"fp64": 8, "fp32": 4, "hilo": 4, "s16": 2}
 
 
 def kernel_source_hash() -> str:
-    """sha256 (first 16 hex digits) of the library sources with comments and
-    blank lines removed, so that an edit of a comment keeps the counter
-    figures taken on the same code."""
+    """sha256 (first 16 hex digits) of the sources that define the kernels and
+    their launches (csrc/ without the C ABI file maclab_api.hip, which holds
+    host code only), with comments and blank lines removed, so that an edit
+    of a comment or of host code keeps the counter figures taken on the same
+    kernels."""
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(ROOT, "paper_1901_02716_amd", "csrc", "*"))):
+        if os.path.basename(p) == "maclab_api.hip":
+            continue
         text = open(p, encoding="utf-8").read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
         text = re.sub(r"//[^\n]*", "", text)
