@@ -143,8 +143,8 @@ int maclab_params(maclab_t h, double out[6]);
  * (so every row starts on a 128-byte boundary); for D3Q19 it is the next of
  * 64, 128, 256 when that is at most nx + nx/8, else nx. The
  * plane stride is px ny nz rounded up to 512, plus 256 elements. The library
- * never reads the padding (row ends and plane ends) and keeps it zero in its
- * own buffers. save copies the state to caller device memory; load
+ * gives no result that depends on the padding (row ends and plane ends) and
+ * keeps it zero in its own buffers. save copies the state to caller device memory; load
  * restores it bitwise into both ping-pong buffers (including 16-bit
  * storage), so a run resumed from a saved state repeats the original bit for
  * bit (for S16 the rounding stream is keyed by the step counter, which load
