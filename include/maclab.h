@@ -167,7 +167,7 @@ int maclab_load_state(maclab_t h, const void* src_device);
  *    the links of the neighbouring rows it needs itself (no LDS, no
  *    barriers); W in {1,2,4,8} wavefronts per workgroup; nyb = pf = 1.
  *  kernel 3: fast D2Q9 (walled x of any extent, or periodic x whose extent
- *    is a multiple of 64*W): one wavefront per (x-segment of 64*W nodes,
+ *    is a multiple of W): one wavefront per (x-segment of 64*W nodes,
  *    band of rows), W in {1,2}; nzb bands; nyb (reported: segments per
  *    row) and pf are ignored.
  * set_tiling validates (nyb <= rows, nzb <= planes or bands <= rows) and
@@ -276,7 +276,7 @@ int maclab_get_adjoint_tiling(maclab_t h, int out[3]);
  *                 schedule a loop over single lattices would use).
  *  get_tiling:    out[3] = {kx, rows, work items}. set_tiling: kx in {1,2},
  *                 rows >= 4 (a periodic x extent must be a multiple of
- *                 64*kx). autotune: times every candidate (each launched
+ *                 kx). autotune: times every candidate (each launched
  *                 `reps` times into the spare buffers, so nothing advances;
  *                 an untimed pass over the spare buffers before each timed
  *                 launch leaves the source out of the caches, as in a step),

@@ -134,12 +134,16 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src, typename C::elem* 
   const int xb = x0 + KX * lane;
   // the segment spans the row (one wavefront): neighbours wrap through DPP;
   // otherwise the edge lanes evaluate the node just outside the segment
-  // (wrapping on a periodic axis, whose extent is then a multiple of 64*KX)
+  // (wrapping on a periodic axis). On a periodic axis the lanes past the end
+  // of the row load its first nodes again, so the last node's right
+  // neighbour is in the next lane (the extent is a multiple of KX).
   const bool full_row = x0 == 0 && lt.nx == SW;
   const bool need_left = !full_row && (x0 > 0 || lt.xper);
   const bool need_right = !full_row && (x0 + SW < lt.nx || lt.xper);
   int hx = lane == 0 ? x0 - 1 : x0 + SW;
-  hx = hx < 0 ? hx + lt.nx : (hx >= lt.nx ? hx - lt.nx : hx);
+  hx = ((hx % lt.nx) + lt.nx) % lt.nx;
+  const int xl = lt.xper ? xb % lt.nx : xb;  // the position this lane loads
+  const bool in_row = lt.xper || xb < lt.nx;
   const bool halo_lane = (lane == 0 && need_left) || (lane == 63 && need_right);
   auto ywrap = [&](int y) { return lt.yper ? (y + lt.ny) % lt.ny : y; };
 
@@ -150,7 +154,7 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src, typename C::elem* 
   E hring[3][3];
   auto load_row = [&](int y, bool valid, V (&ld)[3], E (&hld)[3]) {
     const int rb = (int)((int64_t)lt.pitch * ywrap(y) * EB);
-    const int off = valid && xb < lt.nx ? rb + xb * EB : kOutOfRange;
+    const int off = valid && in_row ? rb + xl * EB : kOutOfRange;
 #pragma unroll
     for (int f = 0; f < 3; ++f) ld[f] = buf_load<V>(rs[f], off);
     const int hoff = valid && halo_lane ? rb + hx * EB : kOutOfRange;
@@ -301,9 +305,7 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src, typename C::elem* 
 bool fast2d_supported(const Layout& L, const StepParams& p) {
   if (L.q != 9 || L.ny < 3) return false;
   if (L.plane * L.bytes >= (int64_t(1) << 31)) return false;  // buffer offsets are 31-bit
-  // periodic x: whole segments only (the extent a multiple of 64)
-  if (!p.fixed[0]) return L.nx % 64 == 0;
-  return L.nx >= 3;
+  return p.fixed[0] ? L.nx >= 3 : L.nx >= 1;
 }
 
 // Wider segments need more registers than a wavefront can hold without
@@ -315,14 +317,14 @@ bool fast2d_shape_valid(const Layout& L, const StepParams& p, const Fast2DShape&
   if (L.px % sh.kx != 0) return false;  // a lane's KX nodes are one vector access
   const int nyo = p.fixed[1] ? (int)L.ny - 2 : (int)L.ny;
   if (sh.nband > nyo) return false;
-  if (!p.fixed[0] && L.nx % (64 * sh.kx) != 0) return false;
+  if (!p.fixed[0] && L.nx % sh.kx != 0) return false;  // a periodic wrap may not split a lane's nodes
   return true;
 }
 
 Fast2DShape fast2d_default_shape(const Layout& L, const StepParams& p, int cus) {
   Fast2DShape sh;
   sh.kx = L.nx >= 128 ? 2 : 1;
-  while (!p.fixed[0] && L.nx % (64 * sh.kx) != 0) sh.kx /= 2;
+  while (!p.fixed[0] && L.nx % sh.kx != 0) sh.kx /= 2;
   const int nseg = (int)((L.nx + 64 * sh.kx - 1) / (64 * sh.kx));
   const int nyo = p.fixed[1] ? (int)L.ny - 2 : (int)L.ny;
   int nband = (8 * cus + nseg - 1) / nseg;  // about 8 wavefronts per CU

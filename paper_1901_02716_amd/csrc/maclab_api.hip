@@ -924,11 +924,10 @@ int batch_plan(maclab_batch_t b, int kx, int rows, std::vector<Lattice2D>* table
     const StepParams p = make_params(h);
     if (!fast2d_supported(h->L, p))
       return bfail(b, MACLAB_EUNSUPPORTED,
-                   "lattice %d: not a fast D2Q9 lattice (a periodic x extent must be a multiple of 64, and a "
-                   "field plane under 2 GiB)", i);
-    if (!p.fixed[0] && h->L.nx % (64 * kx) != 0)
-      return bfail(b, MACLAB_EINVAL, "lattice %d: periodic x extent %lld is not a multiple of %d", i,
-                   (long long)h->L.nx, 64 * kx);
+                   "lattice %d: not a fast D2Q9 lattice (a field plane must be under 2 GiB)", i);
+    if (!p.fixed[0] && h->L.nx % kx != 0)
+      return bfail(b, MACLAB_EINVAL, "lattice %d: periodic x extent %lld is not a multiple of kx = %d", i,
+                   (long long)h->L.nx, kx);
     Lattice2D& t = (*table)[i];
     t.nx = (int)h->L.nx;
     t.ny = (int)h->L.ny;

@@ -512,6 +512,10 @@ FAST2D = [
     ("periodic_256x50", 256, 50, False, (0.2, -0.1)),
     # walled, odd width: at W = 2 the last lane's second node is row padding
     ("walled_131x40", 131, 40, True, (0.0, 0.0)),
+    # periodic widths that are not a multiple of 64: lanes past the end of the
+    # row load its first nodes again (two segments; one shorter than a wavefront)
+    ("periodic_100x30", 100, 30, False, (0.1, 0.05)),
+    ("periodic_40x40", 40, 40, False, (0.0, 0.0)),
 ]
 
 
@@ -574,7 +578,9 @@ def test_d2q9_rows_are_padded_and_the_padding_stays_zero(precision, elem):
 def test_fast2d_is_the_default_for_cavities():
     sim = make_sim(workloads.cavity_2d(n=200, Re=50.0, U=0.1), "fp32")
     assert sim.tiling()["kernel"] == "fast2d"
-    gen = make_sim(workloads.random_field(9, (37, 23, 1), seed=1), "fp32")  # periodic, ragged width
+    rag = make_sim(workloads.random_field(9, (37, 23, 1), seed=1), "fp32")  # periodic, odd width
+    assert rag.tiling() == {"kernel": "fast2d", "W": 1, "nyb": 1, "nzb": rag.tiling()["nzb"], "pf": 0}
+    gen = make_sim(workloads.random_field(9, (37, 2, 1), seed=1), "fp32")  # two rows: the general kernel
     assert gen.tiling()["kernel"] == "general"
 
 
