@@ -1103,9 +1103,11 @@ int maclab_batch_init(const maclab_config* cfgs, int count, void* workspace, siz
     maclab_batch_destroy(b);
     return rc;
   }
+  // two nodes per lane only if every lattice is wide enough for it and of
+  // even width (an odd periodic row cannot be split in pairs)
   b->kx = 2;
   for (int i = 0; i < count; ++i)
-    if (B.L[i].nx < 128) b->kx = 1;
+    if (B.L[i].nx < 128 || B.L[i].nx % 2) b->kx = 1;
   *out = b;
   return MACLAB_OK;
 }

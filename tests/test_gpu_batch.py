@@ -65,6 +65,72 @@ def test_batch_graph_tiling_and_schedule_are_bitwise_identical():
         assert torch.equal(_state(b[i]), want[i])
 
 
+def _mixed_cases():
+    """A cavity, periodic boxes of odd and even widths that are not multiples
+    of 64 (with body forces), and a channel periodic in x only."""
+    cav = workloads.cavity_2d(n=50, Re=80.0, U=0.1)
+    a = workloads.random_field(9, (37, 23, 1), seed=5, amp=0.03)
+    a.G = (0.02, -0.01, 0.0)
+    c = workloads.random_field(9, (100, 30, 1), seed=6, amp=0.03)
+    c.G = (-0.01, 0.03, 0.0)
+    ch = workloads.channel(nx=70, ny=21, u0=0.05, dpdx=-1e-3)
+    return [cav, a, c, ch]
+
+
+def _alone(case, precision):
+    sim = Simulation(9, case.n, case.dx, case.nu, precision=precision, body_force=case.G)
+    sim.set_fields(case.rho, case.u)
+    for face, (rb, ub) in case.fixed.items():
+        sim.set_bc(face, rb, ub)
+    return sim
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "s16"])
+def test_batch_of_mixed_lattices(precision):
+    """Walled and periodic lattices of any width in one batch: each equals,
+    bit for bit, the same lattice stepped alone, at every valid tiling (kx = 2
+    only where every periodic width is even), and the oracle."""
+    from paper_1901_02716_amd import Batch
+
+    cases = _mixed_cases()
+    steps = 23
+
+    def make(cs):
+        b = Batch([(c.n[:2], c.dx, c.nu, c.G) for c in cs], precision=precision)
+        for v, c in zip(b, cs):
+            v.set_fields(c.rho, c.u)
+            for face, (rb, ub) in c.fixed.items():
+                v.set_bc(face, rb, ub)
+        return b
+
+    want = []
+    for c in cases:
+        sim = _alone(c, precision)
+        sim.step(steps)
+        want.append(_state(sim))
+        if precision == "fp64":
+            rho, u = sim.fields()
+            orho, ou = oracle.run(to_problem(c), c.rho, c.u, steps)
+            assert rel_l2(u, ou) < 1e-12 and rel_l2(rho, orho) < 1e-12, c.name
+    for kx, rows in [(1, 4), (1, 9), (2, 5)]:
+        cs = cases if kx == 1 else [c for c in cases if c.n[0] % 2 == 0 or "xlo" in c.fixed]
+        b = make(cs)
+        b.set_tiling(kx, rows)
+        b.step(steps)
+        for v, c in zip(b, cs):
+            assert torch.equal(_state(v), want[cases.index(c)]), (kx, rows, c.name)
+    b = make(cases)
+    with pytest.raises(MaclabError):
+        b.set_tiling(2, 5)  # the 37-wide periodic box cannot take two nodes per lane
+    wide = workloads.random_field(9, (131, 12, 1), seed=7, amp=0.03)  # odd and wide: default kx 1
+    b = make([wide])
+    assert b.tiling()["kx"] == 1
+    b.step(3)
+    sim = _alone(wide, precision)
+    sim.step(3)
+    assert torch.equal(_state(b[0]), _state(sim))
+
+
 def test_batch_autotune_does_not_advance():
     b = cavities(DRAWS, precision="fp32")
     b.step(5)
