@@ -471,17 +471,19 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
   }
   auto zwrap = [&](int z) { return p.zper ? (z + p.nz) % p.nz : z; };
   auto row_off = [&](int z) { return (int)((nx * ((int64_t)yrow + (int64_t)p.ny * zwrap(z)) + xbase) * EB); };
-  // A row that no other workgroup reads (an output row other than the first
-  // and last of the tile, in a plane other than the tile's first two and
-  // last two, which the tiles beside it read as halo) is loaded
+  // An output row other than the first and last of the tile (which the tiles
+  // beside it in y read as halo rows, at about the same time) is loaded
   // non-temporally, so it does not take L2 space from the rows that are read
-  // twice. Every wavefront issues both loads, one of them out of range. With
+  // twice. (The planes a tile shares with its z neighbours are read at the
+  // start of one tile and the end of the other, too far apart for L2 to keep
+  // them, so they are loaded the same way.) Every wavefront issues both
+  // loads, one of them out of range. With
   // a two-plane prefetch or padded rows the second set of loads does not fit
   // in registers: all loads are then cached.
   auto load_plane = [&](int z, bool valid, RawRow<C, KX>& b) {
     const int off = valid && mode != 3 ? row_off(z) : kOutOfRange;
     if constexpr (PF == 1 && !PADX) {
-      const bool once = mode == 0 && wv >= 2 && wv <= rows - 1 && z >= z0 + 1 && z <= z1 - 2;
+      const bool once = mode == 0 && wv >= 2 && wv <= rows - 1;
       const int oc = once ? kOutOfRange : off, on = once ? off : kOutOfRange;
 #pragma unroll
       for (int f = 0; f < 4; ++f) b.f[f] = buf_or(buf_load<V>(rs[f], oc), buf_load<V, 2>(rs[f], on));
