@@ -240,7 +240,7 @@ int maclab_adjoint_result(maclab_t h, const void* state0, const void* adj0, doub
 
 /* Kernel of the reverse step. kernel -1: automatic (the default); 0: the
  * general kernel (any lattice); 3: the fast D2Q9 kernel (walled x of any
- * extent, or periodic x whose extent is a multiple of 64*kx): one
+ * extent, or periodic x whose extent is a multiple of kx): one
  * wavefront per (x-segment of 64*kx nodes, kx in {1,2}, band of rows),
  * 1 <= nband <= ceil(ny/4). get writes {kernel, kx, nband} of the kernel
  * the reverse step uses. EUNSUPPORTED when kernel 3 does not handle the

@@ -156,7 +156,12 @@ __global__ __launch_bounds__(256) void adjoint_d2q9_fast(const typename C::elem*
   const int y1 = (int)((int64_t)(band + 1) * p.ny / p.nband);
   const int xb = x0 + KX * lane;
   const bool wrap_dpp = p.xper && x0 == 0 && p.nx == SW;  // one segment spans a periodic row
-  const bool vec = p.aligned && xb + KX <= p.nx;
+  const bool vec = p.aligned && xb + KX <= p.nx;           // the lane's nodes are one vector
+  // On a periodic axis the lanes past the end of the row read its first nodes
+  // again, so that the last node's right neighbour is in the next lane (the
+  // extent is a multiple of KX); they store nothing and add nothing to dL/dG.
+  const int xw = p.xper ? xb % p.nx : xb;
+  const bool vload = p.aligned && (p.xper || xb + KX <= p.nx);
 
   T P[KX], Mx[KX], My[KX];
   T hP = 0, hMx = 0, hMy = 0;  // node beside the segment (lanes 0 and 63)
@@ -175,11 +180,11 @@ __global__ __launch_bounds__(256) void adjoint_d2q9_fast(const typename C::elem*
     hP = hMx = hMy = (T)0;
     if (!valid) return;  // outside a fixed face: nothing flows from there
     const int64_t rb = p.pitch * rr;
-    if (vec) {
+    if (vload) {
       using V = RowVecT<T, KX>;
-      const V a = *reinterpret_cast<const V*>(bn1 + rb + xb);
-      const V b = *reinterpret_cast<const V*>(bn1 + p.plane + rb + xb);
-      const V c = *reinterpret_cast<const V*>(bn1 + 2 * p.plane + rb + xb);
+      const V a = *reinterpret_cast<const V*>(bn1 + rb + xw);
+      const V b = *reinterpret_cast<const V*>(bn1 + p.plane + rb + xw);
+      const V c = *reinterpret_cast<const V*>(bn1 + 2 * p.plane + rb + xw);
 #pragma unroll
       for (int e = 0; e < KX; ++e) {
         P[e] = a.v[e];
@@ -189,7 +194,7 @@ __global__ __launch_bounds__(256) void adjoint_d2q9_fast(const typename C::elem*
     } else {
 #pragma unroll
       for (int e = 0; e < KX; ++e) {
-        const int x = xb + e;
+        const int x = p.xper ? (xb + e) % p.nx : xb + e;
         if (x < p.nx) {
           P[e] = bn1[rb + x];
           Mx[e] = bn1[p.plane + rb + x];
@@ -199,13 +204,8 @@ __global__ __launch_bounds__(256) void adjoint_d2q9_fast(const typename C::elem*
     }
     if (!wrap_dpp && (lane == 0 || lane == 63)) {
       int hx = lane == 0 ? x0 - 1 : x0 + SW;
-      bool ok = true;
-      if (hx < 0 || hx >= p.nx) {
-        if (p.xper)
-          hx = hx < 0 ? hx + p.nx : hx - p.nx;
-        else
-          ok = false;
-      }
+      if (p.xper) hx = ((hx % p.nx) + p.nx) % p.nx;
+      const bool ok = hx >= 0 && hx < p.nx;
       if (ok) {
         hP = bn1[rb + hx];
         hMx = bn1[p.plane + rb + hx];
@@ -267,8 +267,10 @@ __global__ __launch_bounds__(256) void adjoint_d2q9_fast(const typename C::elem*
     if (r >= y0 && r < y1) {
 #pragma unroll
       for (int e = 0; e < KX; ++e) {
-        gx += (double)Mx[e];
-        gy += (double)My[e];
+        if (xb + e < p.nx) {
+          gx += (double)Mx[e];
+          gy += (double)My[e];
+        }
       }
     }
     T vx[KX], vy[KX];
@@ -453,21 +455,20 @@ hipError_t launch_adjoint_step(const Layout& L, const void* sn, const void* an1,
 }
 
 bool adjoint2d_supported(const Layout& L, const StepParams& p) {
-  if (L.q != 9 || L.ny < 3 || L.nx < 3) return false;
-  return p.fixed[0] || L.nx % 64 == 0;
+  return L.q == 9 && L.ny >= 3 && L.nx >= (p.fixed[0] ? 3 : 1);
 }
 
 bool adjoint2d_shape_valid(const Layout& L, const StepParams& p, const Fast2DShape& sh) {
   if (!adjoint2d_supported(L, p) || (sh.kx != 1 && sh.kx != 2) || sh.nband < 1) return false;
   if (sh.nband > (L.ny + 3) / 4) return false;  // slot budget, and at least ~4 rows per band
-  if (!p.fixed[0] && L.nx % (64 * sh.kx) != 0) return false;
+  if (!p.fixed[0] && L.nx % sh.kx != 0) return false;  // a periodic wrap may not split a lane's nodes
   return true;
 }
 
 Fast2DShape adjoint2d_default_shape(const Layout& L, const StepParams& p, int cus) {
   Fast2DShape sh;
   sh.kx = L.nx >= 128 ? 2 : 1;
-  while (!p.fixed[0] && L.nx % (64 * sh.kx) != 0) sh.kx /= 2;
+  while (!p.fixed[0] && L.nx % sh.kx != 0) sh.kx /= 2;
   const int nseg = (int)((L.nx + 64 * sh.kx - 1) / (64 * sh.kx));
   int nband = (8 * cus + nseg - 1) / nseg;
   const int maxb = (int)((L.ny + 3) / 4);
