@@ -162,6 +162,14 @@ __global__ __launch_bounds__(256) void adjoint_d2q9_fast(const typename C::elem*
   // extent is a multiple of KX); they store nothing and add nothing to dL/dG.
   const int xw = p.xper ? xb % p.nx : xb;
   const bool vload = p.aligned && (p.xper || xb + KX <= p.nx);
+  // the node beside the segment that lanes 0 and 63 read (wrapped on a
+  // periodic axis; none beyond a fixed face)
+  int hx = lane == 0 ? x0 - 1 : x0 + SW;
+  if (p.xper) hx = ((hx % p.nx) + p.nx) % p.nx;
+  const bool hok = !wrap_dpp && (lane == 0 || lane == 63) && hx >= 0 && hx < p.nx;
+  bool node_in[KX];  // the lane's nodes that are nodes of the row (not wrapped copies)
+#pragma unroll
+  for (int e = 0; e < KX; ++e) node_in[e] = xb + e < p.nx;
 
   T P[KX], Mx[KX], My[KX];
   T hP = 0, hMx = 0, hMy = 0;  // node beside the segment (lanes 0 and 63)
@@ -202,15 +210,10 @@ __global__ __launch_bounds__(256) void adjoint_d2q9_fast(const typename C::elem*
         }
       }
     }
-    if (!wrap_dpp && (lane == 0 || lane == 63)) {
-      int hx = lane == 0 ? x0 - 1 : x0 + SW;
-      if (p.xper) hx = ((hx % p.nx) + p.nx) % p.nx;
-      const bool ok = hx >= 0 && hx < p.nx;
-      if (ok) {
-        hP = bn1[rb + hx];
-        hMx = bn1[p.plane + rb + hx];
-        hMy = bn1[2 * p.plane + rb + hx];
-      }
+    if (hok) {
+      hP = bn1[rb + hx];
+      hMx = bn1[p.plane + rb + hx];
+      hMy = bn1[2 * p.plane + rb + hx];
     }
   };
   auto load_u = [&](int j) {
@@ -267,7 +270,7 @@ __global__ __launch_bounds__(256) void adjoint_d2q9_fast(const typename C::elem*
     if (r >= y0 && r < y1) {
 #pragma unroll
       for (int e = 0; e < KX; ++e) {
-        if (xb + e < p.nx) {
+        if (node_in[e]) {
           gx += (double)Mx[e];
           gy += (double)My[e];
         }
