@@ -1,9 +1,11 @@
-// Fast D3Q19 MacLAB step for gfx950 (lattices whose x extent is 64, 128 or
-// 256 nodes; FP32 arithmetic; FP32, split-bf16 or scaled-binary16 storage).
+// Fast D3Q19 MacLAB step for gfx950 (rows of 64, 128 or 256 nodes, or rows
+// between fixed x faces padded to one of those widths; FP32 arithmetic; FP32,
+// split-bf16 or scaled-binary16 storage).
 //
 // Work decomposition
-//  - A wavefront owns one whole x-row: lane l holds the KX = nx/64 nodes
-//    x = KX*l .. KX*l + KX-1, so every field row is one coalesced vector load.
+//  - A wavefront owns one whole x-row: lane l holds the KX = px/64 nodes
+//    x = KX*l .. KX*l + KX-1 (px the row pitch), so every field row is one
+//    coalesced vector load.
 //  - A workgroup is W output rows (y) plus one halo row on each side, one
 //    wavefront per row, marching in z over a chunk of planes (2.5-D blocking).
 //  - Each node computes the equilibria of its 19 links once (Eq. (2), in the
@@ -20,7 +22,8 @@
 //    never written, and a fixed node at either end of a row is written back
 //    with its unchanged stored value.
 //  - Workgroups are numbered so that each XCD gets a contiguous band of tiles
-//    (neighbouring tiles share halo rows through that XCD's L2).
+//    (neighbouring tiles share halo rows through that XCD's L2); rows that no
+//    other workgroup reads are loaded non-temporally, to leave L2 to those.
 #include "internal.h"
 
 #include <type_traits>
