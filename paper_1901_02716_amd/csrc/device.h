@@ -159,7 +159,11 @@ struct CodecS16 {
 
 // Counter-based random bits for CodecS16: a 32-bit integer finaliser of a
 // Weyl sequence over the node index, offset by a key that mixes the seed and
-// the step (computed once per launch on the host).
+// the step (computed once per launch on the host). The finaliser is the
+// xorshift-multiply hash "lowbias32" published by C. Wellons (hash-prospector,
+// 2018); the Weyl increments 0x9e3779b9 / 0x9e3779b1 are 2^32 divided by the
+// golden ratio (Knuth's multiplicative hashing). Every node draws its own
+// 32 bits per step.
 __host__ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;

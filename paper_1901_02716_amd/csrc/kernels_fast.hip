@@ -100,10 +100,13 @@ struct PlaneAcc {
 // sums times K = the codec's density scale (a power of two; see node_links),
 // so K drho' = div36(a.r) and S u~' = S (a.m + 36 K g) / (36 K rho_ref + a.r)
 // for the velocity scale S: every scale is exact, and the stored values
-// carry them. The rounding bits of node e are hb ^ (e * 0x9e3779b9).
+// carry them. Node e of the lane (dense node index node0 + e) draws its own
+// rounding bits, sr_node_bits(key, node0 + e), the bits every kernel gives
+// that node in that step, so the rounding decisions of neighbouring nodes are
+// independent.
 template <class C, int KX>
 __device__ __forceinline__ void finalize_row(const PlaneAcc<KX>& a, float rho_ref, float g36x, float g36y, float g36z,
-                                             uint32_t hb, RowVec<C, KX> (&o)[4]) {
+                                             uint32_t key, int64_t node0, RowVec<C, KX> (&o)[4]) {
 #pragma clang fp contract(off)
   constexpr float K = C::kScaleRho;
   float v[4][KX];
@@ -115,7 +118,7 @@ __device__ __forceinline__ void finalize_row(const PlaneAcc<KX>& a, float rho_re
     v[1][e] = (a.mx[e] + K * g36x) * inv;
     v[2][e] = (a.my[e] + K * g36y) * inv;
     v[3][e] = (a.mz[e] + K * g36z) * inv;
-    bits[e] = hb ^ ((uint32_t)e * 0x9e3779b9u);
+    bits[e] = needs_rng<C>::value ? sr_node_bits(key, node0 + e) : 0u;
   }
   if constexpr (sizeof(typename C::elem) == 2 && KX % 2 == 0) {
     struct Words { uint32_t w[KX / 2]; };
@@ -543,12 +546,10 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
     const int zd = zs - 1;
     V o[4] = {};
     if (STORE && out_row) {
-      // rounding bits of the row's nodes: one hash of the lane's first node,
-      // spread to its KX nodes by distinct odd constants
-      uint32_t hb = 0;
-      if constexpr (needs_rng<C>::value)
-        hb = sr_node_bits(p.sr_key, (int64_t)p.nxd * ((int64_t)yrow + (int64_t)p.ny * zwrap(zd)) + xbase);
-      finalize_row<C, KX>(am, p.rho_ref, p.g36x, p.g36y, p.g36z, hb, o);
+      // dense index of the lane's first node (the stochastic rounding numbers
+      // nodes without the row padding)
+      const int64_t node0 = (int64_t)p.nxd * ((int64_t)yrow + (int64_t)p.ny * zwrap(zd)) + xbase;
+      finalize_row<C, KX>(am, p.rho_ref, p.g36x, p.g36y, p.g36z, p.sr_key, node0, o);
       if constexpr (PADX) {
 #pragma unroll
         for (int e = 0; e < KX; ++e) {
@@ -706,9 +707,8 @@ __global__ __launch_bounds__(64 * NWV) void step_d3q19_indep(const typename C::e
     const int zd = zs - 1;
     if (zd >= z0) {
       const int64_t node0 = nx * ((int64_t)y + (int64_t)p.ny * zwrap(zd)) + xbase;
-      const uint32_t hb = needs_rng<C>::value ? sr_node_bits(p.sr_key, node0) : 0u;  // as the exchange kernel
       RowVec<C, KX> o[4];
-      finalize_row<C, KX>(am, p.rho_ref, p.g36x, p.g36y, p.g36z, hb, o);
+      finalize_row<C, KX>(am, p.rho_ref, p.g36x, p.g36y, p.g36z, p.sr_key, node0, o);
 #pragma unroll
       for (int f = 0; f < 4; ++f) store_row<C, KX>(dst + f * plane + node0, o[f], lane, p.xwall);
     }

@@ -6,8 +6,10 @@ exact new velocity is u~ = g everywhere (Eq. (5) with the force term; the
 density is unchanged), and 2^6 g is chosen between two binary16 neighbours.
 Every node must then store one of the two neighbours, the fraction that
 rounds up must match the position of 2^6 g between them (unbiased rounding),
-and the decisions of two fields at one node must be independent. Each fast
-kernel and the general kernel are checked.
+and the decisions of two fields at one node, and of one field at two
+neighbouring nodes of a row, must be independent. Each fast kernel (the
+exchange kernel with one, two and four nodes per lane) and the general kernel
+are checked.
 """
 import numpy as np
 import pytest
@@ -37,7 +39,8 @@ def _one_step(q, n, kernel):
     return rho, u / e * 64.0  # the stored scaled velocity
 
 
-@pytest.mark.parametrize("q,n,kernel", [(19, (64, 16, 16), "exchange"), (9, (128, 128, 1), "fast2d"),
+@pytest.mark.parametrize("q,n,kernel", [(19, (64, 16, 16), "exchange"), (19, (128, 16, 12), "exchange"),
+                                        (19, (256, 16, 16), "exchange"), (9, (128, 128, 1), "fast2d"),
                                         (19, (24, 11, 7), "general")])
 def test_stochastic_rounding_is_unbiased_and_independent(q, n, kernel):
     rho, v = _one_step(q, n, kernel)
@@ -63,3 +66,12 @@ def test_stochastic_rounding_is_unbiased_and_independent(q, n, kernel):
     corr = np.corrcoef(ups[0], ups[1])[0, 1]
     print(f"  correlation of the two fields' decisions {corr:.4f} (bound {5 / np.sqrt(N):.4f})", flush=True)
     assert abs(corr) < 5 / np.sqrt(N)
+    # and so are the decisions of one field at neighbouring nodes of a row
+    # (nodes held by one lane and by neighbouring lanes alike)
+    for c in (0, 1):
+        up = ups[c].reshape(n[2], n[1], n[0])
+        a, b = up[..., :-1].ravel(), up[..., 1:].ravel()
+        cn = np.corrcoef(a, b)[0, 1]
+        print(f"  field {c + 1}: correlation of neighbouring nodes {cn:.4f} (bound {5 / np.sqrt(a.size):.4f})",
+              flush=True)
+        assert abs(cn) < 5 / np.sqrt(a.size)
