@@ -19,8 +19,13 @@ Output: one JSON line with
     most 16), each on its own copy;
   - `variants` (S16, HILO), `adjoint` (the 512^2 D2Q9 reverse mode against
     the forward), `batch` (512 D2Q9 cavities in one launch per step against
-    one launch per cavity), `launch_bound` (a 64^2 lattice) and
-    `steady_state` (the paper's 2-D cavity run to a steady state).
+    one launch per cavity), `launch_bound` (a 64^2 lattice),
+    `steady_state` (the paper's 2-D cavity run to a steady state),
+    `cavity1024` (the 1024^2 2-D cavity in FP64 and FP32), `parity_cube64`
+    (each storage against the oracle's stored 64^3 run) and `conservation`
+    (mass and momentum drift on a periodic box).
+Every timed run starts after ADVANCE untimed steps from rest, then the
+autotuner, then --warmup steps.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -82,6 +87,12 @@ def updated_nodes(case) -> int:
     return n
 
 
+# Untimed steps before every timed run, whatever --warmup says: the lattice
+# starts at rest (mostly exact zeros, which the memory system moves faster),
+# so every figure is taken on the same partly developed state.
+ADVANCE = 1000
+
+
 def time_variant(case, precision, steps, warmup, autotune=True, tiling=None, copy=False):
     import torch
 
@@ -91,6 +102,7 @@ def time_variant(case, precision, steps, warmup, autotune=True, tiling=None, cop
     sim.set_fields(case.rho, case.u)
     for face, (rb, ub) in case.fixed.items():
         sim.set_bc(face, rb, ub)
+    sim.step(ADVANCE)
     if tiling is not None:
         sim.set_tiling(*tiling)
     elif autotune:
@@ -301,9 +313,91 @@ def time_steady(tol: float = 1e-10, check_every: int = 5000):
             "wall_s": round(wall, 3), "mlups": round(lu / wall / 1e6, 1)}
 
 
-def _oracle_steps(workload: str, steps: int) -> float:
+def time_cavity1024(steps: int, warmup: int):
+    """The 2-D lid-driven cavity of 1024^2 nodes (Re = 1000, lid 0.1) in FP64
+    and FP32 storage. Its state (12.6 MB in FP32, 25 MB in FP64) stays in the
+    256 MB last-level cache, so the rate is an effective one, not HBM."""
+    case = make_case(WORKLOADS["cavity1024"])
+    lu = updated_nodes(case)
+    out = {"workload": WORKLOADS["cavity1024"]["desc"], "updated_nodes_per_step": lu}
+    for prec in ("fp64", "fp32"):
+        ms, _, info = time_variant(case, prec, steps, warmup)
+        b_lu = 2 * 3 * BYTES[prec]
+        out[prec] = {"mlups": round(lu / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 5),
+                     "bytes_per_lattice_update": b_lu,
+                     "effective_gbs": round(b_lu * lu / (ms * 1e-3) / 1e9, 1), "tiling": info["tiling"]}
+    return out
+
+
+def parity_cube64(precisions=("fp32", "hilo", "s16")):
+    """Error of each storage against the FP64 oracle's 5000-step run of the
+    64^3 lid-driven cube at Re = 98.8 (the lattice Reynolds number of the
+    256^3 Re = 400 cube), stored in tests/golden/cube64_re98.8.npz (every 4th
+    node per axis): relative L2 of u and of the density deviation rho - 1."""
+    import numpy as np
+
+    from paper_1901_02716_amd import Simulation
+
+    path = os.path.join(ROOT, "tests", "golden", "cube64_re98.8.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    case = make_case(WORKLOADS["cube64"])
+    out = {"workload": WORKLOADS["cube64"]["desc"] + ", 5000 steps, every 4th node per axis"}
+    for prec in precisions:
+        sim = Simulation(case.q, case.n, case.dx, case.nu, precision=prec, seed=5)
+        sim.set_fields(case.rho, case.u)
+        for face, (rb, ub) in case.fixed.items():
+            sim.set_bc(face, rb, ub)
+        sim.step(5000)
+        rho, u = sim.fields()
+        sim.close()
+        r, v = rho[::4, ::4, ::4], u[:, ::4, ::4, ::4]
+        rr, rv = ref["rho_sub"], ref["u_sub"]
+        rel = lambda a, b: float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))  # noqa: E731
+        out[prec] = {"rel_l2_u": rel(v, rv), "rel_l2_drho": rel(r - 1.0, rr - 1.0)}
+    return out
+
+
+def conservation(steps: int = 2000):
+    """Mass and momentum drift of the periodic 512^2 D2Q9 box (the adjoint
+    workload, no force): Eqs. (4)-(5) conserve both exactly, so the drift is
+    the storage's rounding."""
+    import numpy as np
+
+    from paper_1901_02716_amd import Simulation, workloads
+
+    case, _ = workloads.adjoint_case()
+    out = {"workload": f"D2Q9 periodic 512^2 nu=0.005 Fourier-mode field, {steps} steps"}
+    for prec in ("fp64", "fp32", "s16"):
+        sim = Simulation(9, case.n, case.dx, case.nu, precision=prec, seed=2)
+        sim.set_fields(case.rho, case.u)
+        d0 = np.array(sim.diagnostics())
+        sim.step(steps)
+        d1 = np.array(sim.diagnostics())
+        sim.close()
+        pscale = float(np.sqrt(2.0 * d0[0] * d0[4]))  # bounds sum |rho u_i|
+        out[prec] = {"mass_rel_drift": float(abs(d1[0] - d0[0]) / d0[0]),
+                     "momentum_drift_over_sqrt_2ME": float(np.max(np.abs(d1[1:3] - d0[1:3])) / pscale)}
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_steps(workload: str, steps: int, core: int = -1) -> float:
     """Seconds the FP64 oracle (single-threaded C) takes for `steps` steps of
-    a workload lattice, from its initial state."""
+    a workload lattice, from its initial state, pinned to host core `core`
+    (if >= 0)."""
+    if core >= 0:
+        os.sched_setaffinity(0, {core})
     import oracle
 
     case = make_case(WORKLOADS[workload])
@@ -315,31 +409,35 @@ def _oracle_steps(workload: str, steps: int) -> float:
     return time.perf_counter() - t0
 
 
-def host_cores() -> int:
+def host_cores() -> list:
     """Host cores to run the oracle on: those this process may use, at most
     16 (the host share of one GPU)."""
     try:
-        n = len(os.sched_getaffinity(0))
+        cores = sorted(os.sched_getaffinity(0))
     except AttributeError:
-        n = os.cpu_count() or 1
-    return max(1, min(16, n))
+        cores = list(range(os.cpu_count() or 1))
+    return cores[:16] or [0]
 
 
-def cpu_baseline(workload: str, steps: int, procs: int):
-    """The FP64 oracle on `steps` steps of the workload lattice, as `procs`
-    independent processes at once (one per host core, each on its own copy).
-    They are child processes that import only the oracle and the input
-    generators, so none of them touches the GPU. Returns the aggregate MLUPS,
-    the slowest process's seconds and the per-process seconds."""
+def cpu_baseline(workload: str, steps: int, cores: list):
+    """The FP64 oracle on `steps` steps of the workload lattice, as one
+    independent process per listed host core at once, each pinned to its core
+    and working on its own copy. They are child processes that import only
+    the oracle and the input generators, so none of them touches the GPU.
+    Returns the aggregate MLUPS, the slowest process's seconds and the
+    per-process seconds."""
     import subprocess
 
     import oracle
 
     oracle.build()  # once, before the workers load it
-    code = f"import sys; sys.path.insert(0, {ROOT!r}); import bench; print(bench._oracle_steps({workload!r}, {steps}))"
+    procs = len(cores)
     env = dict(os.environ, OMP_NUM_THREADS="1")
-    workers = [subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE, text=True, env=env)
-               for _ in range(procs)]
+    workers = []
+    for c in cores:
+        code = (f"import sys; sys.path.insert(0, {ROOT!r}); import bench; "
+                f"print(bench._oracle_steps({workload!r}, {steps}, {c}))")
+        workers.append(subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE, text=True, env=env))
     secs = []
     for w in workers:
         out, _ = w.communicate()
@@ -375,6 +473,8 @@ def main(argv=None):
     ap.add_argument("--variants", default="s16,hilo", help="extra storage variants to time ('' for none)")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes of the CPU baseline (0: host cores, at most 16)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 1024^2 cavity, the 64^3 parity run and the conservation run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-steady", action="store_true", help="skip the steady-state run of the 2-D cavity")
     ap.add_argument("--no-autotune", action="store_true", help="use the default tiling")
@@ -426,16 +526,25 @@ def main(argv=None):
     batch = time_batch(args.batch_steps, max(10, args.batch_steps // 4)) if args.batch_steps > 0 else None
     small = time_small() if args.batch_steps > 0 else None
     steady = time_steady() if args.batch_steps > 0 and not args.no_steady else None
+    extras = not args.no_extras and args.workload == "cube256"
+    cavity = time_cavity1024(args.steps, args.warmup) if extras else None
+    parity = parity_cube64() if extras else None
+    drift = conservation() if extras else None
 
     cpu = None
     if not args.no_cpu_baseline:
-        procs = args.cpu_procs or host_cores()
-        cm, cdt, csecs = cpu_baseline(args.workload, args.cpu_steps, procs)
+        cores = host_cores()
+        if args.cpu_procs:
+            cores = cores[:args.cpu_procs]
+        procs = len(cores)
+        cm, cdt, csecs = cpu_baseline(args.workload, args.cpu_steps, cores)
         cpu = {"value": round(cm, 3), "unit": "MLUPS", "cores": procs, "kind": "oracle",
                "sample": f"{args.cpu_steps} FP64 steps of the same {wl['desc']} lattice in each of {procs} "
-                         f"single-threaded oracle processes at once ({procs} x {args.cpu_steps * lu} lattice "
+                         f"single-threaded oracle processes at once, each pinned to its own core "
+                         f"({procs} x {args.cpu_steps * lu} lattice "
                          f"updates; slowest {cdt:.1f} s, fastest {min(csecs):.1f} s; one process alone: "
-                         f"about {args.cpu_steps * lu / min(csecs) / 1e6:.2f} MLUPS)"}
+                         f"about {args.cpu_steps * lu / min(csecs) / 1e6:.2f} MLUPS)",
+               "cpu_model": cpu_model(), "pinned_cores": cores}
 
     if args.profile_copy_mib > 0:
         n = args.profile_copy_mib << 20
@@ -473,6 +582,10 @@ def main(argv=None):
         "batch": batch,
         "launch_bound": small,
         "steady_state": steady,
+        "cavity1024": cavity,
+        "parity_cube64": parity,
+        "conservation": drift,
+        "untimed_advance_steps": ADVANCE,
         "diagnostics_after": {"mass": diag[0], "max_u_over_e": diag[5], "nonfinite": diag[6]},
         "wall_s": round(wall, 3),
         "kernel_source_hash": kernel_source_hash(),

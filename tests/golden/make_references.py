@@ -22,10 +22,18 @@ their results are stored in compact form:
 * ``adjoint512_fd.json`` -- D2Q9 periodic 512^2 box, nu = 0.005, initial
   velocity a sum of 8 random Fourier modes (seed 1), target the same
   construction with seed 2, G = 0, 2000 steps, loss sum (u(T) - u_target)^2:
-  the loss and central differences (h = 1e-4) of it along 16 unit
-  directions in u0 and 16 in G (seed 3).
+  the loss and central differences of it along 16 unit directions in u0 and
+  16 in G (seed 3), each at h = 1e-4 and at 2h. Their difference bounds the
+  error of the difference at h (the truncation error of a central difference
+  falls by 4 from 2h to h, so it is about a third of the difference; rounding
+  in the loss adds a part that grows as 1/h). Two directions (the smallest
+  |derivative| in u0 and in G) are also differenced at h = 1e-5 and 1e-6, to
+  show the rounding floor that rules out the smaller steps.
+* ``batch512_stable.npz`` -- the three largest cavities of the 512-cavity
+  draw (seed 4) whose lattice Reynolds number U dx / nu is at most 2.5,
+  2000 steps each: diagnostics and every 4th node per axis of rho and u.
 
-Usage: python tests/golden/make_references.py {cube64,cube64_re400,cavity1024,adjoint512 [workers]}
+Usage: python tests/golden/make_references.py {cube64,cube64_re400,cavity1024,adjoint512 [workers],batch512}
 """
 from __future__ import annotations
 
@@ -127,10 +135,9 @@ def cavity1024(resume=None):
 
 
 def _loss(args):
-    which, k, sign = args
+    which, k, sign, h = args
     case, tgt = workloads.adjoint_case()
     du, dG = workloads.adjoint_directions()
-    h = 1e-4
     u0 = case.u.copy()
     G = np.zeros(3)
     if which == "u":
@@ -146,22 +153,63 @@ def _loss(args):
 def adjoint512(workers=6):
     from multiprocessing import Pool
 
-    jobs = [("base", 0, 0)] + [(w, k, s) for w in ("u", "G") for k in range(16) for s in (1, -1)]
-    t0 = time.time()
-    with Pool(workers) as pool:
-        res = dict(pool.map(_loss, jobs))
     h = 1e-4
+    ref = json.load(open(os.path.join(HERE, "adjoint512_fd.json")))
+    small = (("u", int(np.argmin(np.abs(ref["fd_u"])))), ("G", int(np.argmin(np.abs(ref["fd_G"])))))
+    jobs = [("base", 0, 0, 0.0)]
+    jobs += [(w, k, s, hh) for hh in (h, 2 * h) for w in ("u", "G") for k in range(16) for s in (1, -1)]
+    jobs += [(w, k, s, hh) for hh in (1e-5, 1e-6) for w, k in small for s in (1, -1)]
+    t0 = time.time()
+    res = {}
+    with Pool(workers) as pool:
+        for args, L in pool.imap_unordered(_loss, jobs):
+            res[args] = L
+            print(f"adjoint512: {len(res)}/{len(jobs)} after {time.time() - t0:.0f} s", flush=True)
+
+    def fd(w, k, hh):
+        return (res[(w, k, 1, hh)] - res[(w, k, -1, hh)]) / (2 * hh)
+
     out = {"case": "D2Q9 periodic 512^2, nu 0.005, 2000 steps, modes seed 1, target seed 2, G = 0",
-           "h": h, "loss": res[("base", 0, 0)],
-           "fd_u": [(res[("u", k, 1)] - res[("u", k, -1)]) / (2 * h) for k in range(16)],
-           "fd_G": [(res[("G", k, 1)] - res[("G", k, -1)]) / (2 * h) for k in range(16)],
+           "h": h, "loss": res[("base", 0, 0, 0.0)],
+           "fd_u": [fd("u", k, h) for k in range(16)],
+           "fd_G": [fd("G", k, h) for k in range(16)],
+           "fd_u_2h": [fd("u", k, 2 * h) for k in range(16)],
+           "fd_G_2h": [fd("G", k, 2 * h) for k in range(16)],
+           "small_h": [{"dir": w, "index": k, "h": hh, "fd": fd(w, k, hh)} for hh in (1e-5, 1e-6) for w, k in small],
            "seconds": time.time() - t0}
     json.dump(out, open(os.path.join(HERE, "adjoint512_fd.json"), "w"), indent=1)
+
+
+def _batch_run(i):
+    N, Re, U = workloads.batch_draw()[i]
+    case = workloads.cavity_2d(n=N, Re=Re, U=U)
+    p = problem(case)
+    rho, u = oracle.run(p, case.rho, case.u, 2000)
+    return i, oracle.diagnostics(p, rho, u), rho[0, ::4, ::4], u[:, 0, ::4, ::4]
+
+
+def batch512(workers=3):
+    from multiprocessing import Pool
+
+    draws = workloads.batch_draw()
+    stable = sorted(((N, i) for i, (N, Re, U) in enumerate(draws) if Re / (N - 1) <= 2.5), reverse=True)[:3]
+    idx = [i for _, i in stable]
+    t0 = time.time()
+    with Pool(workers) as pool:
+        res = pool.map(_batch_run, idx)
+    out = {"index": np.array(idx), "steps": 2000, "stride": 4, "seconds": time.time() - t0}
+    for i, d, r, u in res:
+        out[f"diag_{i}"] = d
+        out[f"rho_sub_{i}"] = r
+        out[f"u_sub_{i}"] = u
+    np.savez_compressed(os.path.join(HERE, "batch512_stable.npz"), **out)
 
 
 if __name__ == "__main__":
     oracle.build()
     if sys.argv[1] == "adjoint512":
         adjoint512(int(sys.argv[2]) if len(sys.argv) > 2 else 6)
+    elif sys.argv[1] == "batch512":
+        batch512()
     else:
         {"cube64": cube64, "cube64_re400": cube64_re400, "cavity1024": cavity1024}[sys.argv[1]]()

@@ -48,7 +48,9 @@ def test_committed_traffic_figures_are_keyed_by_the_hash():
 
 
 def test_cpu_baseline_runs_oracle_workers():
-    mlups, slowest, secs = bench.cpu_baseline("cube64", 1, 2)
-    assert len(secs) == 2 and slowest == max(secs) > 0
-    assert mlups == 2 * 62 ** 3 / slowest / 1e6
-    assert 1 <= bench.host_cores() <= 16
+    cores = bench.host_cores()
+    assert 1 <= len(cores) <= 16
+    mlups, slowest, secs = bench.cpu_baseline("cube64", 1, cores[:2])
+    assert len(secs) == len(cores[:2]) and slowest == max(secs) > 0
+    assert mlups == len(cores[:2]) * 62 ** 3 / slowest / 1e6
+    assert bench.cpu_model()

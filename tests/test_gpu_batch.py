@@ -7,6 +7,8 @@ tiling, with or without graphs and with the one-launch-per-lattice schedule;
 and the FP32 results of stable cavities must match the FP64 oracle to 1e-5
 relative L2.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -197,3 +199,41 @@ def test_full_batch_512_cavities_sampled_against_oracle():
     nonfinite = sum(1 for i in range(len(draws)) if b[i].diagnostics()[6] > 0)
     print(f"  non-finite cavities after {steps} steps: {nonfinite} of 512", flush=True)
     assert np.isfinite(b[stable[0][1]].diagnostics()[0])
+
+
+STABLE_FILE = os.path.join(os.path.dirname(__file__), "golden", "batch512_stable.npz")
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(not os.path.exists(STABLE_FILE), reason="oracle reference not generated")
+def test_full_batch_512_largest_stable_cavities_2000_steps():
+    """The 512-cavity draw (seed 4) advanced together for 2000 steps through
+    the autotuned, graph-replayed batch step: its three largest cavities with
+    lattice Reynolds number U dx / nu <= 2.5 (N = 511, 510 and 510) against the
+    FP64 oracle's 2000-step runs of the same cavities (stored by
+    tests/golden/make_references.py): every 4th node per axis to 1e-5 relative
+    L2, and the mass, momentum and energy sums over all nodes (mass 1e-6,
+    energy 1e-4 relative; momentum 1e-5 of sqrt(2 M E), which bounds
+    sum |rho u_i|)."""
+    ref = np.load(STABLE_FILE)
+    steps = int(ref["steps"])
+    draws = workloads.batch_draw()
+    print(f"[batch] 512 cavities, {steps} steps, reference cavities {list(ref['index'])}", flush=True)
+    b = cavities(draws, precision="fp32")
+    b.autotune(reps=2)
+    b.step(steps)
+    for i in ref["index"]:
+        i = int(i)
+        rho, u = b[i].fields()
+        er = rel_l2(rho[0, ::4, ::4], ref[f"rho_sub_{i}"])
+        eu = rel_l2(u[:, 0, ::4, ::4], ref[f"u_sub_{i}"])
+        d, od = np.array(b[i].diagnostics()), ref[f"diag_{i}"]
+        print(f"  cavity {i} N={draws[i][0]}: relL2 u {eu:.2e} rho {er:.2e}; diagnostics {d[:5]} vs {od[:5]}",
+              flush=True)
+        assert eu < 1e-5 and er < 1e-5, (i, eu, er)
+        assert d[0] == pytest.approx(od[0], rel=1e-6)
+        # |sum rho u_i| <= sqrt(M 2E) (Cauchy-Schwarz) sets the scale of the momentum sums
+        assert np.all(np.abs(d[1:3] - od[1:3]) <= 1e-5 * np.sqrt(2.0 * od[0] * od[4]))
+        assert d[4] == pytest.approx(od[4], rel=1e-4)
+        assert d[6] == 0
+    b.close()
