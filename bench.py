@@ -349,11 +349,12 @@ def parity_cube64(precisions=("fp32", "hilo", "s16")):
         sim.set_fields(case.rho, case.u)
         for face, (rb, ub) in case.fixed.items():
             sim.set_bc(face, rb, ub)
-        sim.step(5000)
+        sim.step(int(ref["steps"]))
         rho, u = sim.fields()
         sim.close()
-        r, v = rho[::4, ::4, ::4], u[:, ::4, ::4, ::4]
-        rr, rv = ref["rho_sub"], ref["u_sub"]
+        st = int(ref["stride"])
+        r, v = rho[::st, ::st, ::st], u[:, ::st, ::st, ::st]
+        rr, rv = ref["rho"], ref["u"]
         rel = lambda a, b: float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))  # noqa: E731
         out[prec] = {"rel_l2_u": rel(v, rv), "rel_l2_drho": rel(r - 1.0, rr - 1.0)}
     return out
