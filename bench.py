@@ -21,7 +21,8 @@ Output: one JSON line with
     the forward), `batch` (512 D2Q9 cavities in one launch per step against
     one launch per cavity), `launch_bound` (a 64^2 lattice),
     `steady_state` (the paper's 2-D cavity run to a steady state),
-    `cavity1024` (the 1024^2 2-D cavity in FP64 and FP32), `parity_cube64`
+    `cavity1024` (the 1024^2 2-D cavity in FP64 and FP32), `bgk` (the tau = 1
+    population scheme on the same cube, 152 against 32 bytes per update), `parity_cube64`
     (each storage against the oracle's stored 64^3 run) and `conservation`
     (mass and momentum drift on a periodic box).
 Every timed run starts after ADVANCE untimed steps from rest, then the
@@ -329,6 +330,38 @@ def time_cavity1024(steps: int, warmup: int):
     return out
 
 
+def time_bgk(steps: int, warmup: int, maclab_ms: float):
+    """The tau = 1 lattice BGK scheme (populations stored and streamed) on
+    the benchmark cube, FP32: 2 Q x 4 = 152 bytes per lattice update where
+    the MacLAB step moves 2 (d + 1) x 4 = 32. Same advance and warmup as the
+    MacLAB figures."""
+    import torch
+
+    from paper_1901_02716_amd import BGK
+
+    case = make_case(WORKLOADS["cube256"])
+    lu = updated_nodes(case)
+    b = BGK(case.q, case.n, case.dx, case.nu, precision="fp32")
+    b.set_fields(case.rho, case.u)
+    for face, (rb, ub) in case.fixed.items():
+        b.set_bc(face, rb, ub)
+    b.step(ADVANCE + warmup)
+    torch.cuda.synchronize()
+    a, c = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(b.stream)
+    b.step(steps)
+    c.record(b.stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(c) / steps
+    b.close()
+    b_lu = 2 * 19 * 4
+    return {"workload": WORKLOADS["cube256"]["desc"] + " fp32, lattice BGK tau = 1 (populations stored)",
+            "bytes_per_lattice_update": b_lu, "maclab_bytes_per_lattice_update": 32,
+            "mlups": round(lu / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 5),
+            "hbm_frac": round(b_lu * lu / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "maclab_speedup": round(ms / maclab_ms, 3)}
+
+
 def parity_cube64(precisions=("fp32", "hilo", "s16")):
     """Error of each storage against the FP64 oracle's 5000-step run of the
     64^3 lid-driven cube at Re = 98.8 (the lattice Reynolds number of the
@@ -529,6 +562,7 @@ def main(argv=None):
     steady = time_steady() if args.batch_steps > 0 and not args.no_steady else None
     extras = not args.no_extras and args.workload == "cube256"
     cavity = time_cavity1024(args.steps, args.warmup) if extras else None
+    bgk = time_bgk(args.steps, args.warmup, ms) if extras and args.precision == "fp32" else None
     parity = parity_cube64() if extras else None
     drift = conservation() if extras else None
 
@@ -584,6 +618,7 @@ def main(argv=None):
         "launch_bound": small,
         "steady_state": steady,
         "cavity1024": cavity,
+        "bgk": bgk,
         "parity_cube64": parity,
         "conservation": drift,
         "untimed_advance_steps": ADVANCE,

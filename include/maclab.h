@@ -325,6 +325,48 @@ int maclab_residual(maclab_t h, double out[3]);
 int maclab_step_until(maclab_t h, double tol, int64_t max_steps, int64_t check_every, int64_t* done,
                       double resid[3]);
 
+/* ----------------------------------------------- lattice BGK with tau = 1
+ * The population scheme the paper starts from: Eq. (1), the lattice BGK
+ * equation, with relaxation time tau = 1, so that a step streams the Q
+ * populations of every node and relaxes them fully to the equilibrium of
+ * Eq. (2):  f_a(x + c_a, t + 1) = f_eq_a(rho(x, t), u(x, t)),  with
+ * rho = sum_a f_a and rho u = sum_a e_a f_a (+ dt G, the body force of
+ * test 2, as in maclab_step). The Methods show that with tau = 1 this gives
+ * the same rho and u as the MacLAB step (Eqs. (9)-(10)); it stores Q values
+ * per node instead of d + 1, which is the memory the paper's method saves
+ * (abstract, advantage (ii)). A handle of its own:
+ *  - cfg as for maclab_init; precision MACLAB_FP64 or MACLAB_FP32 (the
+ *    populations are stored and computed in that type), else
+ *    MACLAB_EUNSUPPORTED. maclab_bgk_workspace_bytes returns 0 for an
+ *    invalid or unsupported configuration.
+ *  - State: two buffers of Q planes, node (i, j, k) at i + nx (j + ny k) of a
+ *    plane (no row padding), plane stride maclab_bgk_state_bytes / (Q x
+ *    element size), holding the post-collision populations as deviations
+ *    f_a - w_a rho_ref. save_state copies the current buffer to caller device
+ *    memory (stream-ordered).
+ *  - set_bc: periodic or fixed faces only (MACLAB_EINVAL otherwise); a fixed
+ *    node holds f_eq(rho_b, u_b) and is never updated, the lowest-numbered
+ *    face owning edges and corners, as in maclab_set_bc.
+ *  - set_fields: the populations become f_eq of the given physical (rho, u)
+ *    (SoA FP64, as for maclab_set_fields); get_fields returns the moments
+ *    of the stored populations, rho = sum_a f_a and u = sum_a e_a f_a / rho.
+ *    Host pointers (on_device = 0) synchronise the stream.
+ *  - step: n steps, stream-ordered and asynchronous; MACLAB_EINVAL if the
+ *    faces of an axis differ.
+ * The workspace is caller-owned device memory (256-byte aligned); the handle
+ * owns nothing else on the device. */
+typedef struct maclab_bgk_s* maclab_bgk_t;
+size_t maclab_bgk_workspace_bytes(const maclab_config* cfg);
+int maclab_bgk_init(const maclab_config* cfg, maclab_bgk_t* out);
+int maclab_bgk_set_bc(maclab_bgk_t h, int face, int kind, double rho_b, const double* u_b);
+int maclab_bgk_set_fields(maclab_bgk_t h, const double* rho, const double* u, int on_device);
+int maclab_bgk_step(maclab_bgk_t h, int64_t n);
+int maclab_bgk_get_fields(maclab_bgk_t h, double* rho, double* u, int on_device);
+size_t maclab_bgk_state_bytes(maclab_bgk_t h);
+int maclab_bgk_save_state(maclab_bgk_t h, void* dst_device);
+void maclab_bgk_destroy(maclab_bgk_t h);
+const char* maclab_bgk_last_error(maclab_bgk_t h);
+
 /* Releases the handle (not the caller's memory). NULL is ignored. */
 void maclab_destroy(maclab_t h);
 

@@ -2,7 +2,8 @@
 (Zhou, arXiv:1901.02716) as hand-written HIP kernels for gfx950 behind a
 small C ABI (include/maclab.h), with a thin ctypes binding.
 
-``Simulation`` wraps one library handle. ``workloads`` builds seeded
+``Simulation`` wraps one library handle; ``BGK`` wraps the tau = 1
+population scheme the method replaces. ``workloads`` builds seeded
 synthetic inputs. The library is loaded lazily; using it without a built
 ``libmaclab.so`` or without a GPU raises.
 """
@@ -19,6 +20,10 @@ def __getattr__(name):
         from . import batch
 
         return getattr(batch, name)
+    if name == "BGK":
+        from .bgk import BGK
+
+        return BGK
     if name == "rollout":
         from .adjoint import rollout
 

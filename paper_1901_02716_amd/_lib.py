@@ -24,8 +24,10 @@ SYMBOLS = (
     "maclab_get_adjoint_tiling", "maclab_batch_workspace_bytes", "maclab_batch_init", "maclab_batch_lattice",
     "maclab_batch_count", "maclab_batch_step", "maclab_batch_step_separate", "maclab_batch_get_tiling",
     "maclab_batch_set_tiling", "maclab_batch_set_graph", "maclab_batch_autotune", "maclab_batch_destroy",
-    "maclab_batch_last_error", "maclab_residual", "maclab_step_until", "maclab_copy", "maclab_destroy",
-    "maclab_last_error",
+    "maclab_batch_last_error", "maclab_residual", "maclab_step_until", "maclab_copy",
+    "maclab_bgk_workspace_bytes", "maclab_bgk_init", "maclab_bgk_set_bc", "maclab_bgk_set_fields",
+    "maclab_bgk_step", "maclab_bgk_get_fields", "maclab_bgk_state_bytes", "maclab_bgk_save_state",
+    "maclab_bgk_destroy", "maclab_bgk_last_error", "maclab_destroy", "maclab_last_error",
 )
 
 
@@ -115,6 +117,20 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.maclab_residual.argtypes = [H, dp]
     lib.maclab_step_until.argtypes = [H, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
                                       ctypes.POINTER(ctypes.c_int64), dp]
+    lib.maclab_bgk_workspace_bytes.restype = ctypes.c_size_t
+    lib.maclab_bgk_workspace_bytes.argtypes = [ctypes.POINTER(Config)]
+    lib.maclab_bgk_init.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(H)]
+    lib.maclab_bgk_set_bc.argtypes = [H, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp]
+    lib.maclab_bgk_set_fields.argtypes = [H, vp, vp, ctypes.c_int]
+    lib.maclab_bgk_step.argtypes = [H, ctypes.c_int64]
+    lib.maclab_bgk_get_fields.argtypes = [H, vp, vp, ctypes.c_int]
+    lib.maclab_bgk_state_bytes.restype = ctypes.c_size_t
+    lib.maclab_bgk_state_bytes.argtypes = [H]
+    lib.maclab_bgk_save_state.argtypes = [H, vp]
+    lib.maclab_bgk_destroy.restype = None
+    lib.maclab_bgk_destroy.argtypes = [H]
+    lib.maclab_bgk_last_error.restype = ctypes.c_char_p
+    lib.maclab_bgk_last_error.argtypes = [H]
     lib.maclab_destroy.restype = None
     lib.maclab_destroy.argtypes = [H]
     lib.maclab_last_error.restype = ctypes.c_char_p
@@ -127,6 +143,12 @@ def load(path: str | None = None) -> ctypes.CDLL:
 def check_batch(rc: int, batch=None) -> None:
     if rc != OK:
         msg = load().maclab_batch_last_error(batch)
+        raise MaclabError(rc, msg.decode() if msg else "")
+
+
+def check_bgk(rc: int, handle=None) -> None:
+    if rc != OK:
+        msg = load().maclab_bgk_last_error(handle)
         raise MaclabError(rc, msg.decode() if msg else "")
 
 

@@ -131,4 +131,22 @@ hipError_t launch_adjoint_result(const Layout& L, const void* s0, const void* ad
 hipError_t launch_adjoint_fold(const double* slots, int64_t nslots, double* out, hipStream_t s);
 hipError_t launch_zero_doubles(double* dst, int64_t count, hipStream_t s);
 
+// Lattice BGK with tau = 1, populations stored (kernels_bgk.hip): Q planes
+// of `plane` elements, dense rows, FP64 or FP32 deviations F_a - w_a rho_ref.
+struct BgkParams {
+  int64_t nx, ny, nz;   // node counts
+  int64_t plane;        // elements between population planes
+  int fixed[3];         // 1 if both faces of the axis are fixed
+  double rho_ref;       // density the stored deviations refer to
+  double g[3];          // dt G / e
+};
+hipError_t launch_bgk_step(int q, bool fp64, const BgkParams& p, const void* src, void* dst, hipStream_t s);
+hipError_t launch_bgk_encode(int q, bool fp64, void* dst, int64_t plane, const double* rho, const double* ux,
+                             const double* uy, const double* uz, int64_t first, int64_t count, double rho_ref,
+                             double e, hipStream_t s);
+hipError_t launch_bgk_decode(int q, bool fp64, const void* src, int64_t plane, double* rho, double* ux, double* uy,
+                             double* uz, int64_t first, int64_t count, double rho_ref, double e, hipStream_t s);
+hipError_t launch_bgk_impose(int q, bool fp64, void* b0, void* b1, const BgkParams& p, const FaceValues& fv, double e,
+                             hipStream_t s);
+
 }  // namespace maclab
