@@ -37,6 +37,8 @@ _LIB = os.path.join(_HERE, "libmaclab_oracle.so")
 
 PERIODIC = 0
 FIXED = 1
+RHO_NEUMANN = 2  # holds u_b; density of the nearest interior node
+PRESSURE = 3     # holds rho_b; velocity of the nearest interior node
 FACES = ("xlo", "xhi", "ylo", "yhi", "zlo", "zhi")
 
 
@@ -129,6 +131,15 @@ class Problem:
         self.face_rho[f] = float(rho)
         uu = tuple(float(v) for v in u) + (0.0,) * (3 - len(u))
         self.face_u[f] = uu[:3]
+        return self
+
+    def set_face(self, face: str | int, kind: int, rho: float = 1.0, u=(0.0, 0.0, 0.0)) -> "Problem":
+        """A bounded face of any kind: FIXED holds (rho, u); RHO_NEUMANN holds
+        u and takes the density of the nearest interior node after every
+        step; PRESSURE holds rho and takes the velocity of that node."""
+        self.set_fixed(face, rho, u)
+        f = FACES.index(face) if isinstance(face, str) else int(face)
+        self.face_kind[f] = int(kind)
         return self
 
     def _c(self) -> _Problem:

@@ -35,7 +35,21 @@
  *    faces takes the values of the face with the lowest index in the order
  *    XLO, XHI, YLO, YHI, ZLO, ZHI (so side walls own the edges and corners
  *    of a lid on the highest face).
- *  - Both faces of an axis are either periodic or fixed.
+ *  - Both faces of an axis are either periodic or bounded (fixed or one of
+ *    the two kinds below, in any mix).
+ *  - The paper never gives the density on a wall (only "no calculations are
+ *    needed" there) nor an inflow/outflow condition; two further kinds of
+ *    bounded face generalise test 2:
+ *      RHO_NEUMANN: the face holds its velocity u_b, and its density has a
+ *        zero normal gradient: after every step it takes the new density of
+ *        the nearest interior node;
+ *      PRESSURE: the face holds its density rho_b (the pressure
+ *        p = rho e^2 / 3 of the Methods), and its velocity has a zero normal
+ *        gradient: after every step it takes the new velocity of the
+ *        nearest interior node.
+ *    The nearest interior node of a boundary node moves every index on a
+ *    bounded axis into 1 .. n-2 (for a node on one face, its neighbour along
+ *    the normal; for an edge or a corner, the diagonal one).
  *
  * Build: gcc -std=c11 -O2 -ffp-contract=off -fPIC -shared (no threads, no
  * SIMD intrinsics, no FMA contraction).
@@ -48,6 +62,8 @@
 
 #define ORACLE_PERIODIC 0
 #define ORACLE_FIXED 1
+#define ORACLE_RHO_NEUMANN 2
+#define ORACLE_PRESSURE 3
 
 /* Problem statement: lattice, node counts, dx, nu (main text, recipe step
  * (i)), a uniform body force, and per-face boundary kind and values. */
@@ -136,20 +152,22 @@ static int validate(const oracle_problem* p) {
   for (int ax = 0; ax < 3; ++ax) {
     if (p->n[ax] < 1) return -1;
     int lo = p->face_kind[2 * ax], hi = p->face_kind[2 * ax + 1];
-    if (lo != hi) return -1;
-    if (lo != ORACLE_PERIODIC && lo != ORACLE_FIXED) return -1;
+    if (lo < ORACLE_PERIODIC || lo > ORACLE_PRESSURE) return -1;
+    if (hi < ORACLE_PERIODIC || hi > ORACLE_PRESSURE) return -1;
+    if ((lo == ORACLE_PERIODIC) != (hi == ORACLE_PERIODIC)) return -1;
     if (ax >= d && (p->n[ax] != 1 || lo != ORACLE_PERIODIC)) return -1;
-    if (lo == ORACLE_FIXED && p->n[ax] < 3) return -1;
+    if (lo != ORACLE_PERIODIC && p->n[ax] < 3) return -1;
   }
   return 0;
 }
 
-/* Index of the lowest-numbered fixed face the node lies on, or -1. */
+/* Index of the lowest-numbered bounded (non-periodic) face the node lies on,
+ * or -1: that face owns the node. */
 static int fixed_face(const oracle_problem* p, int64_t i, int64_t j,
                       int64_t k) {
   const int64_t idx[3] = {i, j, k};
   for (int f = 0; f < 6; ++f) {
-    if (p->face_kind[f] != ORACLE_FIXED) continue;
+    if (p->face_kind[f] == ORACLE_PERIODIC) continue;
     int ax = f / 2;
     int64_t at = (f % 2 == 0) ? 0 : p->n[ax] - 1;
     if (idx[ax] == at) return f;
@@ -162,9 +180,22 @@ static int64_t wrap(int64_t v, int64_t n) {
   return r < 0 ? r + n : r;
 }
 
-/* Writes the fixed-face values (rho_b, u_b) into every fixed node. */
-int oracle_impose_boundary(const oracle_problem* p, double* rho, double* u) {
-  if (validate(p)) return -1;
+/* The nearest interior node of node (i, j, k): every index on a bounded
+ * axis moved into 1 .. n-2. */
+static int64_t interior_of(const oracle_problem* p, int64_t i, int64_t j,
+                           int64_t k) {
+  int64_t idx[3] = {i, j, k};
+  for (int ax = 0; ax < 3; ++ax) {
+    if (p->face_kind[2 * ax] == ORACLE_PERIODIC) continue;
+    if (idx[ax] < 1) idx[ax] = 1;
+    if (idx[ax] > p->n[ax] - 2) idx[ax] = p->n[ax] - 2;
+  }
+  return idx[0] + p->n[0] * (idx[1] + p->n[1] * idx[2]);
+}
+
+/* The values a face holds: all of (rho_b, u_b) on a fixed face, u_b on a
+ * RHO_NEUMANN face, rho_b on a PRESSURE face. */
+static void hold_face_values(const oracle_problem* p, double* rho, double* u) {
   const int d = lattice_dims(p->q);
   const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
   const int64_t N = nx * ny * nz;
@@ -174,9 +205,39 @@ int oracle_impose_boundary(const oracle_problem* p, double* rho, double* u) {
         int f = fixed_face(p, i, j, k);
         if (f < 0) continue;
         int64_t x = i + nx * (j + ny * k);
-        rho[x] = p->face_rho[f];
-        for (int c = 0; c < d; ++c) u[c * N + x] = p->face_u[f][c];
+        if (p->face_kind[f] != ORACLE_RHO_NEUMANN) rho[x] = p->face_rho[f];
+        if (p->face_kind[f] != ORACLE_PRESSURE)
+          for (int c = 0; c < d; ++c) u[c * N + x] = p->face_u[f][c];
       }
+}
+
+/* The zero-normal-gradient values: the density of a RHO_NEUMANN node and the
+ * velocity of a PRESSURE node are those of its nearest interior node. */
+static void copy_from_interior(const oracle_problem* p, double* rho,
+                               double* u) {
+  const int d = lattice_dims(p->q);
+  const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
+  const int64_t N = nx * ny * nz;
+  for (int64_t k = 0; k < nz; ++k)
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) {
+        int f = fixed_face(p, i, j, k);
+        if (f < 0 || p->face_kind[f] == ORACLE_FIXED) continue;
+        int64_t x = i + nx * (j + ny * k);
+        int64_t s = interior_of(p, i, j, k);
+        if (p->face_kind[f] == ORACLE_RHO_NEUMANN)
+          rho[x] = rho[s];
+        else
+          for (int c = 0; c < d; ++c) u[c * N + x] = u[c * N + s];
+      }
+}
+
+/* Writes the boundary values into every boundary node: what each face
+ * holds, then the values its kind takes from the interior. */
+int oracle_impose_boundary(const oracle_problem* p, double* rho, double* u) {
+  if (validate(p)) return -1;
+  hold_face_values(p, rho, u);
+  copy_from_interior(p, rho, u);
   return 0;
 }
 
@@ -232,6 +293,8 @@ static void step_once(const oracle_problem* p, double e, double dt,
         update_node(p, e, dt, rho, u, i, j, k, &rho_new[x], un);
         for (int cc = 0; cc < d; ++cc) u_new[cc * N + x] = un[cc];
       }
+  /* faces with a zero-normal-gradient quantity take it from the new state */
+  copy_from_interior(p, rho_new, u_new);
 }
 
 /* One step evaluated only at the listed nodes (flat indices): rho_out[s] and
@@ -251,9 +314,20 @@ int oracle_step_at(const oracle_problem* p, const double* rho,
     if (x < 0 || x >= N) return -1;
     const int64_t i = x % nx, j = (x / nx) % ny, k = x / (nx * ny);
     double un[3] = {0.0, 0.0, 0.0};
-    if (fixed_face(p, i, j, k) >= 0) {
+    const int f = fixed_face(p, i, j, k);
+    if (f >= 0) {
       rho_out[s] = rho[x];
       for (int cc = 0; cc < d; ++cc) un[cc] = u[cc * N + x];
+      if (p->face_kind[f] != ORACLE_FIXED) {
+        /* the copied quantity is the new value at the nearest interior node */
+        const int64_t t = interior_of(p, i, j, k);
+        double rt, ut[3] = {0.0, 0.0, 0.0};
+        update_node(p, e, dt, rho, u, t % nx, (t / nx) % ny, t / (nx * ny), &rt, ut);
+        if (p->face_kind[f] == ORACLE_RHO_NEUMANN)
+          rho_out[s] = rt;
+        else
+          for (int cc = 0; cc < d; ++cc) un[cc] = ut[cc];
+      }
     } else {
       update_node(p, e, dt, rho, u, i, j, k, &rho_out[s], un);
     }
@@ -367,6 +441,9 @@ int oracle_adjoint_run(const oracle_problem* p, const double* rho0,
                        const double* u_target, double* grad_u0,
                        double* grad_G, double* loss) {
   if (validate(p) || steps < 0) return -1;
+  /* reverse mode covers periodic and fixed faces */
+  for (int f = 0; f < 6; ++f)
+    if (p->face_kind[f] == ORACLE_RHO_NEUMANN || p->face_kind[f] == ORACLE_PRESSURE) return -1;
   const int q = p->q, d = lattice_dims(q);
   const int(*c)[3] = lattice_c(q);
   const double* w = lattice_w(q);

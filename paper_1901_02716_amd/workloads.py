@@ -34,6 +34,10 @@ class Case:
     # face name -> (rho_b, (ux, uy, uz)); faces absent here are periodic
     fixed: dict = field(default_factory=dict)
     steps: int = 1
+    # face name -> "rho_neumann" (holds u_b; density from the nearest interior
+    # node) or "pressure" (holds rho_b; velocity from that node) for faces of
+    # `fixed` that do not hold both values
+    kinds: dict = field(default_factory=dict)
 
     @property
     def d(self) -> int:
@@ -143,6 +147,22 @@ def channel_profile(case: Case, u0: float, dpdx: float, rho: float = 1.0) -> np.
     h = (ny - 1) * case.dx
     y = np.arange(ny) * case.dx
     return u0 / h * y + 1.0 / (2.0 * rho * case.nu) * dpdx * (y * y - h * y)
+
+
+def pressure_channel(nx: int = 11, ny: int = 41, dx: float = 0.05, nu: float = 0.01, drho: float = 2e-4) -> Case:
+    """Channel along y between two plates (the x faces: no-slip, u = 0, with
+    a density of zero normal gradient) driven by a pressure difference: the
+    y faces hold the densities 1 + drho/2 (inlet, y = 0) and 1 - drho/2
+    (outlet) and take their velocity from the nearest interior node. The
+    plates, the lower-numbered faces, own the corners. Starts at rest with
+    the density falling linearly along the channel."""
+    y = np.arange(ny) / (ny - 1)
+    rho = np.broadcast_to((1.0 + drho * (0.5 - y))[:, None], (1, ny, nx)).copy()
+    u = np.zeros((2, 1, ny, nx))
+    fixed = {"xlo": (1.0, (0.0, 0.0, 0.0)), "xhi": (1.0, (0.0, 0.0, 0.0)),
+             "ylo": (1.0 + 0.5 * drho, (0.0, 0.0, 0.0)), "yhi": (1.0 - 0.5 * drho, (0.0, 0.0, 0.0))}
+    kinds = {"xlo": "rho_neumann", "xhi": "rho_neumann", "ylo": "pressure", "yhi": "pressure"}
+    return Case("pressure_channel", 9, (nx, ny, 1), dx, nu, rho, u, fixed=fixed, kinds=kinds)
 
 
 def shear_wave(q: int, n: int, m: int, amp_lattice: float, nu: float = 0.02, dx: float = 0.1,

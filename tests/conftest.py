@@ -20,8 +20,9 @@ def pytest_configure(config):
 def to_problem(case: workloads.Case) -> oracle.Problem:
     """Problem description for the oracle from a workload case."""
     p = oracle.Problem(q=case.q, n=case.n, dx=case.dx, nu=case.nu, G=tuple(case.G))
+    kinds = {"fixed": oracle.FIXED, "rho_neumann": oracle.RHO_NEUMANN, "pressure": oracle.PRESSURE}
     for face, (rb, ub) in case.fixed.items():
-        p.set_fixed(face, rb, ub)
+        p.set_face(face, kinds[case.kinds.get(face, "fixed")], rb, ub)
     return p
 
 

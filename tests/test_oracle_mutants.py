@@ -25,8 +25,17 @@ MUTANTS = {
                      "1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,\n    1.0 / 36.0, 1.0 / 36.0"),
     "d3q19_velocity": ("{-1, 0, 1}, {1, 0, -1}}", "{1, 0, 1}, {1, 0, -1}}"),
     "d2q9_velocity": ("{1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}}", "{1, 1, 0}, {-1, 1, 0}, {1, -1, 0}, {-1, -1, 0}}"),
-    "corner_owner": ("for (int f = 0; f < 6; ++f) {\n    if (p->face_kind[f] != ORACLE_FIXED) continue;",
-                     "for (int f = 5; f >= 0; --f) {\n    if (p->face_kind[f] != ORACLE_FIXED) continue;"),
+    "corner_owner": ("for (int f = 0; f < 6; ++f) {\n    if (p->face_kind[f] == ORACLE_PERIODIC) continue;",
+                     "for (int f = 5; f >= 0; --f) {\n    if (p->face_kind[f] == ORACLE_PERIODIC) continue;"),
+    "neumann_density_not_copied": ("          rho[x] = rho[s];", "          rho[x] = rho[x];"),
+    "pressure_velocity_not_copied": ("for (int c = 0; c < d; ++c) u[c * N + x] = u[c * N + s];",
+                                     "for (int c = 0; c < d; ++c) u[c * N + x] = u[c * N + x];"),
+    "interior_two_nodes_in": ("if (idx[ax] < 1) idx[ax] = 1;", "if (idx[ax] < 2) idx[ax] = 2;"),
+    "interior_periodic_clamped": ("    if (p->face_kind[2 * ax] == ORACLE_PERIODIC) continue;\n    if (idx[ax] < 1)",
+                                  "    if (idx[ax] < 1)"),
+    "derived_faces_not_updated": ("  copy_from_interior(p, rho_new, u_new);\n}", "  (void)rho_new;\n}"),
+    "pressure_density_not_held": ("if (p->face_kind[f] != ORACLE_RHO_NEUMANN) rho[x] = p->face_rho[f];",
+                                  "if (p->face_kind[f] == ORACLE_FIXED) rho[x] = p->face_rho[f];"),
     "energy_half": ("nsum_add(&E, 0.5 * rho[x] * uu);", "nsum_add(&E, rho[x] * uu);"),
     "adjoint_division_sign": ("rt[x] = rb[x] - dot / r1;", "rt[x] = rb[x] + dot / r1;"),
     "adjoint_downstream_index": ("int64_t xi = wrap(i + c[a][0], nx);", "int64_t xi = wrap(i - c[a][0], nx);"),
@@ -53,6 +62,11 @@ def _battery():
     yield pins.test_adjoint_matches_central_differences, {"q": 9, "n": (9, 7, 1), "walls": True}
     yield pins.test_adjoint_matches_central_differences, {"q": 19, "n": (5, 4, 4), "walls": False}
     yield pins.test_adjoint_force_closed_form, {}
+    for q in (9, 19):
+        yield pins.test_derived_faces_copy_the_nearest_interior_node, {"q": q}
+        yield pins.test_shear_wave_through_pressure_faces_keeps_the_exact_factor, {"q": q}
+    yield pins.test_rho_neumann_plates_keep_the_channel_profiles_exact, {"nu": 0.001, "u0": 0.1, "dpdx": -1e-4}
+    yield pins.test_pressure_driven_channel_is_poiseuille, {}
 
 
 def _caught(lib):

@@ -523,3 +523,147 @@ def test_residual_decays_at_the_slowest_mode(oracle_lib):
     M = case.n[1] - 1
     lam = (2 + math.cos(math.pi / M)) / 3
     assert r2 / r1 == pytest.approx(lam ** k, rel=1e-3)
+
+
+# ---------------------------------------- zero-normal-gradient faces (N4)
+
+@pytest.mark.parametrize("nu", [0.01, 0.0006])
+@pytest.mark.parametrize("u0,dpdx", [(0.1, 0.0), (0.0, -1e-4), (0.1, -1e-4)])
+def test_rho_neumann_plates_keep_the_channel_profiles_exact(oracle_lib, nu, u0, dpdx):
+    """Plates that hold their velocity and take the density of the nearest
+    interior node: in a unidirectional shear flow the gathered density is
+    exactly 1 (the density moment of each group of links with one c_y does
+    not depend on u_x, and the u_x^2 terms cancel), so the plates stay at
+    rho = 1 and Eqs. (7)-(8) remain exact steady states at the nodes."""
+    case = workloads.channel(nu=nu, u0=u0, dpdx=dpdx)
+    case.kinds = {"ylo": "rho_neumann", "yhi": "rho_neumann"}
+    prof = workloads.channel_profile(case, u0, dpdx)
+    case.u[0] = prof[None, :, None]
+    rho, u = _run(case, 200)
+    e = oracle.particle_speed(nu, case.dx)
+    tol = 200 * 2.2e-16 * e
+    assert np.abs(u[0, 0] - prof[:, None]).max() < tol
+    assert np.abs(u[1]).max() < tol
+    assert np.abs(rho - 1).max() < 200 * 2.2e-16
+
+
+def _pressure_channel(ny, drho, steps=10000):
+    """Steady pressure-driven channel: the mid-channel profile u_y(x) against
+    Eq. (8) (u0 = 0) with the local pressure gradient (central difference of
+    the density, p = rho e^2 / 3 of the Methods) and with the gradient of the
+    two faces, -(p_in - p_out) / ((ny - 1) dx)."""
+    case = workloads.pressure_channel(ny=ny, drho=drho)
+    p = to_problem(case)
+    rho, u = oracle.run(p, case.rho, case.u, steps)
+    rho1, u1 = oracle.run(p, rho, u, 1)
+    e = oracle.particle_speed(case.nu, case.dx)
+    nx, m, c = case.n[0], ny // 2, case.n[0] // 2
+    h, xx = (nx - 1) * case.dx, np.arange(nx) * case.dx
+
+    def profile(dpdy, r):  # Eq. (8) across the channel
+        return 1.0 / (2.0 * r * case.nu) * dpdy * (xx * xx - h * xx)
+
+    local = e * e / 3.0 * (rho[0, m + 1, c] - rho[0, m - 1, c]) / (2.0 * case.dx)
+    faces = -drho * e * e / 3.0 / ((ny - 1) * case.dx)
+    mid = u[1, 0, m, :]
+    pl, pf = profile(local, rho[0, m, c]), profile(faces, 1.0)
+    err_local = float(np.abs(mid - pl).max() / np.abs(pl).max())
+    err_faces = float(np.abs(mid - pf).max() / np.abs(pf).max())
+    change = float(np.abs(u1 - u).max() / np.abs(u).max())
+    cross = float(np.abs(u[0, 0, m, :]).max() / np.abs(mid).max())
+    return err_local, err_faces, change, cross
+
+
+def test_pressure_driven_channel_is_poiseuille(oracle_lib):
+    """A channel driven by two pressure faces (density held, velocity from the
+    nearest interior node) between plates with a zero-gradient density
+    reaches plane Poiseuille flow, the u0 = 0 case of Eq. (8): at mid-channel
+    the profile matches Eq. (8) with the local pressure gradient to 1e-6
+    (the density varies by 2e-4 along the channel), there is no cross flow,
+    and against the gradient of the two face pressures the profile differs
+    by a pressure loss at the faces of a fixed fraction of a node, so the
+    mismatch halves when the channel doubles in length (2.2e-3 at 40
+    lattices, 1.1e-3 at 80)."""
+    l40 = _pressure_channel(41, 2e-4)
+    l40b = _pressure_channel(41, 4e-4)
+    l80 = _pressure_channel(81, 2e-4)
+    print(f"local {l40[0]:.2e} {l40b[0]:.2e} {l80[0]:.2e}; faces {l40[1]:.3e} {l80[1]:.3e}; change {l80[2]:.1e}")
+    for err_local, err_faces, change, cross in (l40, l40b, l80):
+        assert change < 1e-9  # steady
+        assert err_local < 1e-6
+        assert cross < 1e-6
+        assert err_faces < 3e-3
+    assert l40[1] / l80[1] == pytest.approx(2.0, rel=0.05)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_shear_wave_through_pressure_faces_keeps_the_exact_factor(oracle_lib, q):
+    """A shear flow u_x(y) that crosses two pressure faces (x = 0 and
+    x = N-1, density 1 held, velocity from the nearest interior node) is
+    uniform along x, so each face node copies exactly the velocity of its
+    own row: every node, faces included, decays by the exact factor
+    (2 + cos(2 pi m / N)) / 3 per step and the density stays 1."""
+    n, m, steps = 32, 3, 7
+    case = workloads.shear_wave(q, n, m, 0.2)
+    case.fixed = {"xlo": (1.0, (0.0, 0.0, 0.0)), "xhi": (1.0, (0.0, 0.0, 0.0))}
+    case.kinds = {"xlo": "pressure", "xhi": "pressure"}
+    rho, u = _run(case, steps)
+    G = (2.0 + math.cos(2 * math.pi * m / n)) / 3.0
+    e = oracle.particle_speed(case.nu, case.dx)
+    assert np.abs(rho - 1.0).max() < 1e-14
+    assert np.abs(u[1:]).max() < 1e-15
+    assert np.abs(u[0] - G ** steps * case.u[0]).max() < 1e-14 * e
+
+
+def _derived_box(q):
+    if q == 9:
+        case = workloads.random_field(9, (9, 8, 1), seed=41)
+        case.fixed = {"xlo": (1.01, (0.0, 0.0, 0.0)), "xhi": (0.99, (0.0, 0.0, 0.0)),
+                      "ylo": (1.0, (0.02, 0.0, 0.0)), "yhi": (1.0, (-0.03, 0.01, 0.0))}
+        case.kinds = {"xlo": "pressure", "xhi": "pressure", "ylo": "rho_neumann", "yhi": "rho_neumann"}
+    else:
+        case = workloads.random_field(19, (6, 5, 7), seed=42)
+        case.fixed = {"xlo": (1.0, (0.0, 0.01, 0.0)), "xhi": (1.0, (0.0, 0.0, 0.02)),
+                      "zlo": (1.02, (0.0, 0.0, 0.0)), "zhi": (0.98, (0.0, 0.0, 0.0))}
+        case.kinds = {"xlo": "rho_neumann", "xhi": "fixed", "zlo": "pressure", "zhi": "pressure"}
+    return case
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_derived_faces_copy_the_nearest_interior_node(oracle_lib, q):
+    """Brute force on small boxes with every kind of face (and their edges
+    and corners, owned by the lowest-numbered face): after each step a
+    RHO_NEUMANN node holds its u_b and the new density of its nearest
+    interior node (indices on bounded axes moved into 1..n-2), a PRESSURE
+    node holds its rho_b and that node's new velocity, a fixed node holds
+    both; the one-node evaluation agrees with the full step."""
+    case = _derived_box(q)
+    p = to_problem(case)
+    order = ("xlo", "xhi", "ylo", "yhi", "zlo", "zhi")
+    nx, ny, nz = case.n
+    rho, u = case.rho, case.u
+    for step in range(3):
+        r0, u0 = rho.copy(), u.copy()
+        oracle.impose_boundary(p, r0, u0)
+        rho, u = oracle.run(p, r0, u0, 1)
+        for k in range(nz):
+            for j in range(ny):
+                for i in range(nx):
+                    idx = (i, j, k)
+                    owner = next((f for f in order if f in case.fixed and
+                                  idx["xyz".index(f[0])] == (0 if f[1:] == "lo" else case.n["xyz".index(f[0])] - 1)),
+                                 None)
+                    if owner is None:
+                        continue
+                    kind = case.kinds.get(owner, "fixed")
+                    rb, ub = case.fixed[owner]
+                    cl = [min(max(v, 1), case.n[a] - 2) if any(f[0] == "xyz"[a] for f in case.fixed) else v
+                          for a, v in enumerate(idx)]
+                    ci, cj, ck = cl
+                    want_rho = rho[ck, cj, ci] if kind == "rho_neumann" else rb
+                    want_u = u[:, ck, cj, ci] if kind == "pressure" else np.array(ub[:case.d])
+                    assert rho[k, j, i] == want_rho, (step, idx, owner)
+                    assert np.array_equal(u[:, k, j, i], want_u), (step, idx, owner)
+        nodes = np.arange(case.n[0] * case.n[1] * case.n[2])
+        ro, uo = oracle.step_at(p, r0.ravel(), u0.reshape(case.d, -1), nodes)
+        assert np.array_equal(ro, rho.ravel()) and np.array_equal(uo, u.reshape(case.d, -1))
