@@ -66,12 +66,25 @@ enum { MACLAB_FP64 = 0, MACLAB_FP32 = 1, MACLAB_HILO = 2, MACLAB_S16 = 3 };
 
 /* Faces and boundary kinds. A fixed face holds its physical (rho_b, u_b) on
  * every node of the face ("physical variables can directly be retained as
- * the boundary conditions", abstract (i); recipe step (iv)). Both faces of
- * an axis must be of the same kind. A node on several fixed faces takes the
- * values of the lowest-numbered face (XLO < XHI < YLO < YHI < ZLO < ZHI), so
- * side walls own the edges and corners of a lid on the highest face. */
+ * the boundary conditions", abstract (i); recipe step (iv)). The paper gives
+ * no density for a wall and no inflow or outflow condition; two more kinds
+ * of bounded face generalise the pressure-gradient term of test 2:
+ *  MACLAB_BC_RHO_NEUMANN: the face holds u_b, and its density has a zero
+ *    normal gradient: after every step it takes the new density of the
+ *    nearest interior node (a wall that neither adds nor removes mass
+ *    through a held density);
+ *  MACLAB_BC_PRESSURE: the face holds rho_b, i.e. the pressure
+ *    p = rho_b e^2 / 3 (Methods), and its velocity has a zero normal
+ *    gradient: after every step it takes the new velocity of the nearest
+ *    interior node (a pressure inlet or outlet).
+ * The nearest interior node moves every index on a bounded axis into
+ * 1 .. n-2. Both faces of an axis must be periodic, or both bounded (any mix
+ * of the three bounded kinds). A node on several bounded faces belongs to
+ * the lowest-numbered face (XLO < XHI < YLO < YHI < ZLO < ZHI), so side
+ * walls own the edges and corners of a lid on the highest face. Reverse mode
+ * and batches take periodic and fixed faces only. */
 enum { MACLAB_XLO = 0, MACLAB_XHI, MACLAB_YLO, MACLAB_YHI, MACLAB_ZLO, MACLAB_ZHI };
-enum { MACLAB_BC_PERIODIC = 0, MACLAB_BC_FIXED = 1 };
+enum { MACLAB_BC_PERIODIC = 0, MACLAB_BC_FIXED = 1, MACLAB_BC_RHO_NEUMANN = 2, MACLAB_BC_PRESSURE = 3 };
 
 typedef struct maclab_s* maclab_t;
 
@@ -100,9 +113,11 @@ size_t maclab_workspace_bytes(const maclab_config* cfg);
  * MACLAB_EWORKSPACE / MACLAB_EUNSUPPORTED) before any HIP call. */
 int maclab_init(const maclab_config* cfg, maclab_t* out);
 
-/* Sets face `face` to `kind`. For MACLAB_BC_FIXED the face holds density
- * rho_b and velocity u_b[0..d-1] (physical units); the values are written
- * into the state at once and are never updated by maclab_step. */
+/* Sets face `face` to `kind`. A bounded face holds density rho_b and / or
+ * velocity u_b[0..d-1] (physical units) as its kind says; the held values
+ * are written into the state at once and never updated by maclab_step, the
+ * others are taken from the interior now and after every step.
+ * MACLAB_EUNSUPPORTED for RHO_NEUMANN or PRESSURE on a lattice of a batch. */
 int maclab_set_bc(maclab_t h, int face, int kind, double rho_b, const double* u_b);
 
 /* Loads physical rho (N values) and u (d*N values) into the state, then

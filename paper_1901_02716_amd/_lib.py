@@ -11,7 +11,7 @@ OK, EINVAL, EUNSUPPORTED, EHIP, EWORKSPACE, ENONFINITE = 0, -1, -2, -3, -4, -5
 D2Q9, D3Q19 = 9, 19
 FP64, FP32, HILO, S16 = 0, 1, 2, 3
 XLO, XHI, YLO, YHI, ZLO, ZHI = range(6)
-PERIODIC, FIXED = 0, 1
+PERIODIC, FIXED, RHO_NEUMANN, PRESSURE = 0, 1, 2, 3
 
 # Exported symbols, in the order include/maclab.h declares them.
 SYMBOLS = (

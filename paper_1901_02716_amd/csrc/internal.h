@@ -49,6 +49,11 @@ hipError_t launch_step_generic(const Layout& L, const void* src, void* dst, cons
                                hipStream_t s);
 hipError_t launch_impose_bc(const Layout& L, void* buf0, void* buf1, const FaceValues& fv, double rho_ref,
                             double e, hipStream_t s);
+// Faces with a zero normal gradient (MACLAB_BC_RHO_NEUMANN: density;
+// MACLAB_BC_PRESSURE: velocity) copy it from their nearest interior nodes in
+// `buf`; nothing is launched when no face is of those kinds.
+bool has_derived_faces(const FaceValues& fv);
+hipError_t launch_derive_faces(const Layout& L, void* buf, const FaceValues& fv, hipStream_t s);
 // Dense nodes first .. first+count-1 of one field plane (dense index: x
 // fastest over nx, no row padding) from / to FP64 arrays of count values.
 hipError_t launch_encode(const Layout& L, void* plane_dst, const double* src, int64_t first, int64_t count,

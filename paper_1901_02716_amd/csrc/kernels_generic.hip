@@ -13,6 +13,8 @@
 // The new lattice velocity is u~' = (m' + g) / (rho_ref + drho').
 #include "internal.h"
 
+#include <algorithm>
+
 namespace maclab {
 
 template <class C>
@@ -82,8 +84,10 @@ __global__ __launch_bounds__(256) void step_generic_kernel(const typename C::ele
   if constexpr (D == 3) store_field<C>(dst, p.plane, 3, x, (mz + (T)(36.0 * p.g[2])) * inv, bits);
 }
 
-// Writes the fixed-face values into both buffers; a node on several fixed
-// faces takes the values of the lowest-numbered one.
+// Writes what each bounded face holds into both buffers: (rho_b, u_b) on a
+// fixed face, u_b on a face with a zero-gradient density, rho_b on a pressure
+// face. A node on several bounded faces belongs to the lowest-numbered one.
+// The other values of the last two kinds come from derive_faces_kernel.
 template <class C>
 __global__ void impose_bc_kernel(typename C::elem* b0, typename C::elem* b1, int64_t nx, int64_t ny,
                                  int64_t nz, int64_t px, int64_t plane, int d, FaceValues fv, double rho_ref,
@@ -95,7 +99,7 @@ __global__ void impose_bc_kernel(typename C::elem* b0, typename C::elem* b1, int
     const int64_t x = stored_index(di, nx, px);
     int face = -1;
     for (int f = 0; f < 6 && face < 0; ++f) {
-      if (fv.kind[f] != MACLAB_BC_FIXED) continue;
+      if (fv.kind[f] == MACLAB_BC_PERIODIC) continue;
       const int ax = f / 2;
       if (idx[ax] == ((f & 1) ? n[ax] - 1 : 0)) face = f;
     }
@@ -103,9 +107,54 @@ __global__ void impose_bc_kernel(typename C::elem* b0, typename C::elem* b1, int
     typename C::elem v[4];
     v[0] = C::enc_nearest((typename C::T)(fv.rho[face] - rho_ref), 0);
     for (int c = 0; c < d; ++c) v[1 + c] = C::enc_nearest((typename C::T)(fv.u[face][c] / e), 1 + c);
-    for (int f = 0; f <= d; ++f) {
+    const int first = fv.kind[face] == MACLAB_BC_RHO_NEUMANN ? 1 : 0;
+    const int last = fv.kind[face] == MACLAB_BC_PRESSURE ? 0 : d;
+    for (int f = first; f <= last; ++f) {
       b0[f * plane + x] = v[f];
       b1[f * plane + x] = v[f];
+    }
+  }
+}
+
+// The values of faces with a zero normal gradient: after a step, every node
+// owned by a face with a zero-gradient density takes the stored density of
+// its nearest interior node (each index on a bounded axis moved into
+// 1 .. n-2), and every node of a pressure face that node's stored velocity.
+// Stored elements are copied bit for bit (the same codec on both sides). One
+// thread per node of a face (blockIdx.y = face); the nodes read are interior
+// nodes, which this kernel never writes.
+template <class E>
+__global__ void derive_faces_kernel(E* buf, int64_t nx, int64_t ny, int64_t nz, int64_t px, int64_t plane, int d,
+                                    FaceValues fv) {
+  const int face = blockIdx.y;
+  const int kind = fv.kind[face];
+  if (kind != MACLAB_BC_RHO_NEUMANN && kind != MACLAB_BC_PRESSURE) return;
+  const int64_t n[3] = {nx, ny, nz};
+  const int ax = face / 2, ab = ax == 0 ? 1 : 0, ac = ax == 2 ? 1 : 2;
+  const int64_t count = n[ab] * n[ac];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t idx[3];
+    idx[ax] = (face & 1) ? n[ax] - 1 : 0;
+    idx[ab] = t % n[ab];
+    idx[ac] = t / n[ab];
+    bool owned = true;  // by no lower-numbered bounded face
+    for (int g = 0; g < face; ++g) {
+      if (fv.kind[g] == MACLAB_BC_PERIODIC) continue;
+      if (idx[g / 2] == ((g & 1) ? n[g / 2] - 1 : 0)) owned = false;
+    }
+    if (!owned) continue;
+    int64_t in[3];
+    for (int a = 0; a < 3; ++a) {
+      in[a] = idx[a];
+      if (fv.kind[2 * a] == MACLAB_BC_PERIODIC) continue;
+      in[a] = in[a] < 1 ? 1 : (in[a] > n[a] - 2 ? n[a] - 2 : in[a]);
+    }
+    const int64_t x = idx[0] + px * (idx[1] + ny * idx[2]);
+    const int64_t s = in[0] + px * (in[1] + ny * in[2]);
+    if (kind == MACLAB_BC_RHO_NEUMANN) {
+      buf[x] = buf[s];
+    } else {
+      for (int f = 1; f <= d; ++f) buf[f * plane + x] = buf[f * plane + s];
     }
   }
 }
@@ -315,6 +364,32 @@ hipError_t launch_impose_bc(const Layout& L, void* b0, void* b1, const FaceValue
                        L.nz, L.px, L.plane, L.d, fv, rho_ref, e);
     return hipGetLastError();
   });
+}
+
+bool has_derived_faces(const FaceValues& fv) {
+  for (int f = 0; f < 6; ++f)
+    if (fv.kind[f] == MACLAB_BC_RHO_NEUMANN || fv.kind[f] == MACLAB_BC_PRESSURE) return true;
+  return false;
+}
+
+hipError_t launch_derive_faces(const Layout& L, void* buf, const FaceValues& fv, hipStream_t s) {
+  if (!has_derived_faces(fv)) return hipSuccess;
+  const int64_t big = std::max(L.nx * L.ny, std::max(L.ny * L.nz, L.nx * L.nz));
+  const dim3 grid(blocks_256(big), 2 * L.d);
+  switch (L.bytes) {
+    case 2:
+      hipLaunchKernelGGL((derive_faces_kernel<uint16_t>), grid, dim3(256), 0, s, (uint16_t*)buf, L.nx, L.ny, L.nz,
+                         L.px, L.plane, L.d, fv);
+      break;
+    case 4:
+      hipLaunchKernelGGL((derive_faces_kernel<uint32_t>), grid, dim3(256), 0, s, (uint32_t*)buf, L.nx, L.ny, L.nz,
+                         L.px, L.plane, L.d, fv);
+      break;
+    default:
+      hipLaunchKernelGGL((derive_faces_kernel<uint64_t>), grid, dim3(256), 0, s, (uint64_t*)buf, L.nx, L.ny, L.nz,
+                         L.px, L.plane, L.d, fv);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_encode(const Layout& L, void* dst, const double* src, int64_t first, int64_t count,

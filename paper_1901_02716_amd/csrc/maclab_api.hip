@@ -164,7 +164,7 @@ StepParams make_params(const maclab_t h) {
   p.nz = h->L.nz;
   p.px = h->L.px;
   p.plane = h->L.plane;
-  for (int ax = 0; ax < 3; ++ax) p.fixed[ax] = h->fv.kind[2 * ax] == MACLAB_BC_FIXED;
+  for (int ax = 0; ax < 3; ++ax) p.fixed[ax] = h->fv.kind[2 * ax] != MACLAB_BC_PERIODIC;
   p.rho_ref = h->cfg.rho_ref;
   for (int i = 0; i < 3; ++i) p.g[i] = (i < h->L.d) ? h->dt * h->cfg.body_force[i] / h->e : 0.0;
   p.seed = h->cfg.seed;
@@ -175,17 +175,27 @@ StepParams make_params(const maclab_t h) {
 
 int check_faces(maclab_t h) {
   for (int ax = 0; ax < h->L.d; ++ax) {
-    if (h->fv.kind[2 * ax] != h->fv.kind[2 * ax + 1])
-      return fail(h, MACLAB_EINVAL, "faces of axis %d differ (both must be periodic or both fixed)", ax);
+    if ((h->fv.kind[2 * ax] == MACLAB_BC_PERIODIC) != (h->fv.kind[2 * ax + 1] == MACLAB_BC_PERIODIC))
+      return fail(h, MACLAB_EINVAL, "faces of axis %d differ (both must be periodic or both bounded)", ax);
     const int64_t n = ax == 0 ? h->L.nx : (ax == 1 ? h->L.ny : h->L.nz);
-    if (h->fv.kind[2 * ax] == MACLAB_BC_FIXED && n < 3)
-      return fail(h, MACLAB_EINVAL, "fixed faces on axis %d need at least 3 nodes", ax);
+    if (h->fv.kind[2 * ax] != MACLAB_BC_PERIODIC && n < 3)
+      return fail(h, MACLAB_EINVAL, "bounded faces on axis %d need at least 3 nodes", ax);
   }
   return MACLAB_OK;
 }
 
 int impose(maclab_t h) {
   HIP_TRY(h, launch_impose_bc(h->L, h->state[0], h->state[1], h->fv, h->cfg.rho_ref, h->e, h->stream));
+  HIP_TRY(h, launch_derive_faces(h->L, h->state[0], h->fv, h->stream));
+  HIP_TRY(h, launch_derive_faces(h->L, h->state[1], h->fv, h->stream));
+  return MACLAB_OK;
+}
+
+// Reverse mode covers periodic and fixed faces.
+int reverse_supported(maclab_t h) {
+  if (h->view) return fail(h, MACLAB_EUNSUPPORTED, "reverse mode is not available on a lattice of a batch");
+  if (has_derived_faces(h->fv))
+    return fail(h, MACLAB_EUNSUPPORTED, "reverse mode covers periodic and fixed faces only");
   return MACLAB_OK;
 }
 
@@ -323,16 +333,18 @@ int maclab_set_bc(maclab_t h, int face, int kind, double rho_b, const double* u_
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
   if (face < 0 || face > 5) return fail(h, MACLAB_EINVAL, "face %d out of range", face);
   if (face / 2 >= h->L.d) return fail(h, MACLAB_EINVAL, "face %d does not exist in 2D", face);
-  if (kind != MACLAB_BC_PERIODIC && kind != MACLAB_BC_FIXED)
+  if (kind < MACLAB_BC_PERIODIC || kind > MACLAB_BC_PRESSURE)
     return fail(h, MACLAB_EINVAL, "unknown boundary kind %d", kind);
-  if (kind == MACLAB_BC_FIXED) {
+  if ((kind == MACLAB_BC_RHO_NEUMANN || kind == MACLAB_BC_PRESSURE) && h->view)
+    return fail(h, MACLAB_EUNSUPPORTED, "a lattice of a batch has periodic and fixed faces only");
+  if (kind != MACLAB_BC_PERIODIC) {
     if (!u_b) return fail(h, MACLAB_EINVAL, "u_b is NULL");
     if (!(rho_b > 0) || !isfinite(rho_b)) return fail(h, MACLAB_EINVAL, "rho_b must be finite and positive");
     for (int c = 0; c < h->L.d; ++c)
       if (!isfinite(u_b[c])) return fail(h, MACLAB_EINVAL, "u_b must be finite");
   }
   h->fv.kind[face] = kind;
-  if (kind == MACLAB_BC_FIXED) {
+  if (kind != MACLAB_BC_PERIODIC) {
     h->fv.rho[face] = rho_b;
     for (int c = 0; c < 3; ++c) h->fv.u[face][c] = c < h->L.d ? u_b[c] : 0.0;
   }
@@ -379,6 +391,7 @@ int maclab_step(maclab_t h, int64_t n) {
     const void* src = h->state[h->cur];
     void* dst = h->state[h->cur ^ 1];
     HIP_TRY(h, launch_plan(h->L, p, pl, src, dst, h->stream));
+    HIP_TRY(h, launch_derive_faces(h->L, dst, h->fv, h->stream));
     h->cur ^= 1;
     ++h->steps;
   }
@@ -484,7 +497,8 @@ int maclab_params(maclab_t h, double out[6]) {
   if (!out) return fail(h, MACLAB_EINVAL, "out is NULL");
   double umax = 0;
   for (int f = 0; f < 2 * h->L.d; ++f) {
-    if (h->fv.kind[f] != MACLAB_BC_FIXED) continue;
+    // faces that hold their velocity (a pressure face takes it from the flow)
+    if (h->fv.kind[f] != MACLAB_BC_FIXED && h->fv.kind[f] != MACLAB_BC_RHO_NEUMANN) continue;
     double s = 0;
     for (int c = 0; c < h->L.d; ++c) s += h->fv.u[f][c] * h->fv.u[f][c];
     umax = std::max(umax, sqrt(s));
@@ -633,9 +647,10 @@ int maclab_step_external(maclab_t h, const void* src, void* dst, int64_t step_in
   p.sr_key = sr_key(p.seed, p.step);
   const Plan pl = current_plan(h, p);
   HIP_TRY(h, launch_plan(h->L, p, pl, src, dst, h->stream));
-  bool any_fixed = false;
-  for (int f = 0; f < 6; ++f) any_fixed |= h->fv.kind[f] == MACLAB_BC_FIXED;
-  if (any_fixed) HIP_TRY(h, launch_impose_bc(h->L, dst, dst, h->fv, h->cfg.rho_ref, h->e, h->stream));
+  bool any_bounded = false;
+  for (int f = 0; f < 6; ++f) any_bounded |= h->fv.kind[f] != MACLAB_BC_PERIODIC;
+  if (any_bounded) HIP_TRY(h, launch_impose_bc(h->L, dst, dst, h->fv, h->cfg.rho_ref, h->e, h->stream));
+  HIP_TRY(h, launch_derive_faces(h->L, dst, h->fv, h->stream));
   return MACLAB_OK;
 }
 
@@ -658,7 +673,7 @@ size_t maclab_adjoint_bytes(maclab_t h) {
 
 int maclab_adjoint_seed(maclab_t h, const void* state_T, const double* dLdu, void* adj) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
-  if (h->view) return fail(h, MACLAB_EUNSUPPORTED, "reverse mode is not available on a lattice of a batch");
+  if (int rc_ = reverse_supported(h)) return rc_;
   if (!state_T || !dLdu || !adj) return fail(h, MACLAB_EINVAL, "state_T, dLdu and adj must be device pointers");
   int rc = check_faces(h);
   if (rc) return rc;
@@ -669,7 +684,7 @@ int maclab_adjoint_seed(maclab_t h, const void* state_T, const double* dLdu, voi
 
 int maclab_adjoint_reset(maclab_t h) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
-  if (h->view) return fail(h, MACLAB_EUNSUPPORTED, "reverse mode is not available on a lattice of a batch");
+  if (int rc_ = reverse_supported(h)) return rc_;
   HIP_TRY(h, launch_zero_doubles(h->gslots, (int64_t)(h->L.adjoint_bytes / sizeof(double)), h->stream));
   return MACLAB_OK;
 }
@@ -730,7 +745,7 @@ int maclab_get_adjoint_tiling(maclab_t h, int out[3]) {
 
 int maclab_adjoint_step(maclab_t h, const void* state_n, const void* adj_np1, void* adj_n) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
-  if (h->view) return fail(h, MACLAB_EUNSUPPORTED, "reverse mode is not available on a lattice of a batch");
+  if (int rc_ = reverse_supported(h)) return rc_;
   if (!state_n || !adj_np1 || !adj_n || adj_np1 == adj_n)
     return fail(h, MACLAB_EINVAL, "state and adjoint buffers must be device pointers, adj_np1 != adj_n");
   int rc = check_faces(h);
@@ -742,7 +757,7 @@ int maclab_adjoint_step(maclab_t h, const void* state_n, const void* adj_np1, vo
 int maclab_adjoint_segment(maclab_t h, const void* ckpt, void* states, int64_t nsteps, int64_t step_index,
                            void* adj_a, void* adj_b, int* which) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
-  if (h->view) return fail(h, MACLAB_EUNSUPPORTED, "reverse mode is not available on a lattice of a batch");
+  if (int rc_ = reverse_supported(h)) return rc_;
   if (!ckpt || !adj_a || !adj_b || !which || adj_a == adj_b || (*which != 0 && *which != 1))
     return fail(h, MACLAB_EINVAL, "ckpt, adj_a, adj_b (distinct) and which (0 or 1) are required");
   if (nsteps < 1 || step_index < 0) return fail(h, MACLAB_EINVAL, "nsteps must be >= 1 and step_index >= 0");
@@ -773,7 +788,7 @@ int maclab_adjoint_segment(maclab_t h, const void* ckpt, void* states, int64_t n
 int maclab_adjoint_result(maclab_t h, const void* state0, const void* adj0, double* dLdu0, double* dLdrho0,
                           double dLdG[3]) {
   if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
-  if (h->view) return fail(h, MACLAB_EUNSUPPORTED, "reverse mode is not available on a lattice of a batch");
+  if (int rc_ = reverse_supported(h)) return rc_;
   if (!adj0) return fail(h, MACLAB_EINVAL, "adj0 is NULL");
   if (dLdu0) {
     if (!state0) return fail(h, MACLAB_EINVAL, "state0 is NULL");

@@ -16,6 +16,7 @@ from . import _lib
 
 _PRECISIONS = {"fp64": _lib.FP64, "fp32": _lib.FP32, "hilo": _lib.HILO, "s16": _lib.S16}
 _FACES = {"xlo": 0, "xhi": 1, "ylo": 2, "yhi": 3, "zlo": 4, "zhi": 5}
+_KINDS = {"fixed": _lib.FIXED, "rho_neumann": _lib.RHO_NEUMANN, "pressure": _lib.PRESSURE}
 
 
 def _device_ptr(t: torch.Tensor, nbytes: int, name: str) -> int:
@@ -86,11 +87,15 @@ class Simulation:
         _lib.check(self.lib.maclab_init(ctypes.byref(cfg), ctypes.byref(self.h)))
 
     # -------------------------------------------------------------- set-up
-    def set_bc(self, face, rho_b: float = 1.0, u_b=(0.0, 0.0, 0.0), periodic: bool = False) -> None:
+    def set_bc(self, face, rho_b: float = 1.0, u_b=(0.0, 0.0, 0.0), periodic: bool = False,
+               kind: str = "fixed") -> None:
+        """kind: "fixed" (holds rho_b and u_b), "rho_neumann" (holds u_b; the
+        density of the nearest interior node) or "pressure" (holds rho_b;
+        the velocity of the nearest interior node); periodic=True overrides."""
         f = _FACES[face] if isinstance(face, str) else int(face)
         u = (ctypes.c_double * 3)(*[float(v) for v in (tuple(u_b) + (0.0, 0.0, 0.0))[:3]])
-        kind = _lib.PERIODIC if periodic else _lib.FIXED
-        _lib.check(self.lib.maclab_set_bc(self.h, f, kind, float(rho_b), u), self.h)
+        k = _lib.PERIODIC if periodic else _KINDS[kind]
+        _lib.check(self.lib.maclab_set_bc(self.h, f, k, float(rho_b), u), self.h)
 
     def set_fields(self, rho, u) -> None:
         """rho: N values, u: d*N values (physical units), numpy or torch."""
