@@ -13,6 +13,9 @@ Every function mirrors one step of the paper (Zhou, arXiv:1901.02716):
   dt = dx/e.
 * :func:`run` -- repeated application of Eqs. (4)-(5) [mlb-p.1, mlb-u.1] with
   fixed (Dirichlet) and periodic faces and the body-force term of test 2.
+* :func:`run_extended` -- :func:`run` built with x87 extended precision as
+  the arithmetic type (the same source), to tell the FP64 oracle's own
+  rounding from a GPU path's in long runs of slow flows.
 * :func:`step_at` -- the same step evaluated at sampled nodes only.
 * :func:`diagnostics` -- mass, momentum, kinetic energy, max |u|/e and the
   non-finite count (the conserved moments of Methods, Eqs. (14)-(15)).
@@ -34,6 +37,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "maclab_oracle.c")
 _LIB = os.path.join(_HERE, "libmaclab_oracle.so")
+_LIB_EXT = os.path.join(_HERE, "libmaclab_oracle_ext.so")
 
 PERIODIC = 0
 FIXED = 1
@@ -50,6 +54,14 @@ def build(force: bool = False, extra_flags: tuple[str, ...] = (), out: str | Non
                *extra_flags, _SRC, "-o", out, "-lm"]
         subprocess.run(cmd, check=True)
     return out
+
+
+def build_extended(force: bool = False) -> str:
+    """The same source with x87 extended precision (long double, 64-bit
+    significand) as its arithmetic type: the FP64 oracle's steps with 11
+    more bits, to separate the FP64 oracle's own rounding from a GPU path's
+    in long runs."""
+    return build(force, ('-DORACLE_REAL=long double',), _LIB_EXT)
 
 
 class _Problem(ctypes.Structure):
@@ -226,6 +238,40 @@ def step_at(p: Problem, rho: np.ndarray, u: np.ndarray, nodes) -> tuple[np.ndarr
     if rc != 0:
         raise ValueError("invalid problem or node index")
     return ro, uo
+
+
+_ext_lib: ctypes.CDLL | None = None
+_ldp = ctypes.POINTER(ctypes.c_longdouble)
+
+
+def _load_extended() -> ctypes.CDLL:
+    global _ext_lib
+    if _ext_lib is None:
+        lib = ctypes.CDLL(build_extended())
+        if lib.oracle_real_bytes() != ctypes.sizeof(ctypes.c_longdouble):
+            raise RuntimeError("the extended oracle build does not use long double")
+        lib.oracle_impose_boundary.argtypes = [ctypes.POINTER(_Problem), _ldp, _ldp]
+        lib.oracle_run.argtypes = [ctypes.POINTER(_Problem), _ldp, _ldp, ctypes.c_int64]
+        lib.oracle_particle_speed.restype = ctypes.c_longdouble
+        lib.oracle_particle_speed.argtypes = [ctypes.c_double, ctypes.c_double]
+        _ext_lib = lib
+    return _ext_lib
+
+
+def run_extended(p: Problem, rho0: np.ndarray, u0: np.ndarray, steps: int):
+    """run() in x87 extended precision. The inputs may be float64 or
+    numpy.longdouble; returns numpy.longdouble arrays of the input shapes."""
+    rho = np.ascontiguousarray(rho0, dtype=np.longdouble).copy()
+    u = np.ascontiguousarray(u0, dtype=np.longdouble).copy()
+    assert rho.size == p.N and u.size == p.d * p.N
+    L = _load_extended()
+    c = p._c()
+    if L.oracle_impose_boundary(ctypes.byref(c), rho.ctypes.data_as(_ldp), u.ctypes.data_as(_ldp)) != 0:
+        raise ValueError("invalid problem")
+    rc = L.oracle_run(ctypes.byref(c), rho.ctypes.data_as(_ldp), u.ctypes.data_as(_ldp), int(steps))
+    if rc != 0:
+        raise ValueError(f"oracle_run failed ({rc})")
+    return rho, u
 
 
 def diagnostics(p: Problem, rho: np.ndarray, u: np.ndarray) -> np.ndarray:

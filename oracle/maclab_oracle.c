@@ -54,11 +54,24 @@
  * Build: gcc -std=c11 -O2 -ffp-contract=off -fPIC -shared (no threads, no
  * SIMD intrinsics, no FMA contraction).
  */
-#include <math.h>
 #include <stddef.h>
+#include <tgmath.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* The arithmetic type. FP64 is the oracle; a build with
+ * -DORACLE_REAL="long double" (x87 extended precision, 64-bit significand)
+ * runs the same steps with 11 more bits, which separates the FP64 oracle's
+ * own rounding from a GPU path's in long runs of slow flows. Problem
+ * parameters stay double; every field and every operation is `real`. */
+#ifndef ORACLE_REAL
+#define ORACLE_REAL double
+#endif
+typedef ORACLE_REAL real;
+
+/* sizeof(real): 8 for the FP64 oracle, 16 for the extended build. */
+int oracle_real_bytes(void) { return (int)sizeof(real); }
 
 #define ORACLE_PERIODIC 0
 #define ORACLE_FIXED 1
@@ -87,32 +100,32 @@ typedef struct {
 static const int D2Q9_C[9][3] = {
     {0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
     {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
-static const double D2Q9_W[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
-                                 1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
-                                 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+static const real D2Q9_W[9] = {(real)4 / 9,  (real)1 / 9,  (real)1 / 9,
+                                 (real)1 / 9,  (real)1 / 9,  (real)1 / 36,
+                                 (real)1 / 36, (real)1 / 36, (real)1 / 36};
 
 static const int D3Q19_C[19][3] = {
     {0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
     {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {-1, 1, 0},
     {1, -1, 0}, {0, 1, 1},   {0, -1, -1}, {0, -1, 1}, {0, 1, -1},
     {1, 0, 1},  {-1, 0, -1}, {-1, 0, 1}, {1, 0, -1}};
-static const double D3Q19_W[19] = {
-    1.0 / 3.0,  1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
-    1.0 / 18.0, 1.0 / 18.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
-    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
-    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+static const real D3Q19_W[19] = {
+    (real)1 / 3,  (real)1 / 18, (real)1 / 18, (real)1 / 18, (real)1 / 18,
+    (real)1 / 18, (real)1 / 18, (real)1 / 36, (real)1 / 36, (real)1 / 36,
+    (real)1 / 36, (real)1 / 36, (real)1 / 36, (real)1 / 36, (real)1 / 36,
+    (real)1 / 36, (real)1 / 36, (real)1 / 36, (real)1 / 36};
 
 static int lattice_dims(int q) { return q == 9 ? 2 : (q == 19 ? 3 : 0); }
 
 static const int (*lattice_c(int q))[3] { return q == 9 ? D2Q9_C : D3Q19_C; }
 
-static const double* lattice_w(int q) { return q == 9 ? D2Q9_W : D3Q19_W; }
+static const real* lattice_w(int q) { return q == 9 ? D2Q9_W : D3Q19_W; }
 
-/* Copies the velocity set (q x 3 ints) and weights (q doubles) out. */
-int oracle_lattice(int q, int* c_out, double* w_out) {
+/* Copies the velocity set (q x 3 ints) and weights (q reals) out. */
+int oracle_lattice(int q, int* c_out, real* w_out) {
   if (lattice_dims(q) == 0) return -1;
   const int(*c)[3] = lattice_c(q);
-  const double* w = lattice_w(q);
+  const real* w = lattice_w(q);
   for (int a = 0; a < q; ++a) {
     for (int i = 0; i < 3; ++i) c_out[3 * a + i] = c[a][i];
     w_out[a] = w[a];
@@ -121,25 +134,25 @@ int oracle_lattice(int q, int* c_out, double* w_out) {
 }
 
 /* Eq. (6) [mlb-viscosity]: particle speed from viscosity and lattice size. */
-double oracle_particle_speed(double nu, double dx) { return 6.0 * nu / dx; }
+real oracle_particle_speed(double nu, double dx) { return 6.0 * (real)nu / (real)dx; }
 
 /* Text after Eq. (6): the time step is no longer free, dt = dx / e. */
-double oracle_time_step(double nu, double dx) {
-  return dx / oracle_particle_speed(nu, dx);
+real oracle_time_step(double nu, double dx) {
+  return (real)dx / oracle_particle_speed(nu, dx);
 }
 
 /* Eq. (2) [feq-full] for link a, in physical units with e_a = e c_a. */
-double oracle_feq(int q, int a, double rho, const double* u, double e) {
+real oracle_feq(int q, int a, real rho, const real* u, real e) {
   const int(*c)[3] = lattice_c(q);
-  const double* w = lattice_w(q);
+  const real* w = lattice_w(q);
   const int d = lattice_dims(q);
-  double eu = 0.0, uu = 0.0;
+  real eu = 0.0, uu = 0.0;
   for (int i = 0; i < d; ++i) {
-    double ea_i = e * (double)c[a][i];
+    real ea_i = e * (real)c[a][i];
     eu += ea_i * u[i];
     uu += u[i] * u[i];
   }
-  double e2 = e * e;
+  real e2 = e * e;
   return w[a] * rho *
          (1.0 + 3.0 * eu / e2 + 4.5 * eu * eu / (e2 * e2) - 1.5 * uu / e2);
 }
@@ -195,7 +208,7 @@ static int64_t interior_of(const oracle_problem* p, int64_t i, int64_t j,
 
 /* The values a face holds: all of (rho_b, u_b) on a fixed face, u_b on a
  * RHO_NEUMANN face, rho_b on a PRESSURE face. */
-static void hold_face_values(const oracle_problem* p, double* rho, double* u) {
+static void hold_face_values(const oracle_problem* p, real* rho, real* u) {
   const int d = lattice_dims(p->q);
   const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
   const int64_t N = nx * ny * nz;
@@ -213,8 +226,8 @@ static void hold_face_values(const oracle_problem* p, double* rho, double* u) {
 
 /* The zero-normal-gradient values: the density of a RHO_NEUMANN node and the
  * velocity of a PRESSURE node are those of its nearest interior node. */
-static void copy_from_interior(const oracle_problem* p, double* rho,
-                               double* u) {
+static void copy_from_interior(const oracle_problem* p, real* rho,
+                               real* u) {
   const int d = lattice_dims(p->q);
   const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
   const int64_t N = nx * ny * nz;
@@ -234,7 +247,7 @@ static void copy_from_interior(const oracle_problem* p, double* rho,
 
 /* Writes the boundary values into every boundary node: what each face
  * holds, then the values its kind takes from the interior. */
-int oracle_impose_boundary(const oracle_problem* p, double* rho, double* u) {
+int oracle_impose_boundary(const oracle_problem* p, real* rho, real* u) {
   if (validate(p)) return -1;
   hold_face_values(p, rho, u);
   copy_from_interior(p, rho, u);
@@ -243,27 +256,27 @@ int oracle_impose_boundary(const oracle_problem* p, double* rho, double* u) {
 
 /* Eqs. (4)-(5) at one non-fixed node (i, j, k): gathers the equilibria of
  * the upstream nodes and returns the new density and velocity. */
-static void update_node(const oracle_problem* p, double e, double dt,
-                        const double* rho, const double* u, int64_t i,
-                        int64_t j, int64_t k, double* rho_out,
-                        double* u_out) {
+static void update_node(const oracle_problem* p, real e, real dt,
+                        const real* rho, const real* u, int64_t i,
+                        int64_t j, int64_t k, real* rho_out,
+                        real* u_out) {
   const int q = p->q, d = lattice_dims(q);
   const int(*c)[3] = lattice_c(q);
   const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
   const int64_t N = nx * ny * nz;
-  double r = 0.0;
-  double m[3] = {0.0, 0.0, 0.0};
+  real r = 0.0;
+  real m[3] = {0.0, 0.0, 0.0};
   for (int a = 0; a < q; ++a) {
     /* Source node x - e_a dt = x - c_a. */
     int64_t si = wrap(i - c[a][0], nx);
     int64_t sj = wrap(j - c[a][1], ny);
     int64_t sk = wrap(k - c[a][2], nz);
     int64_t s = si + nx * (sj + ny * sk);
-    double us[3] = {0.0, 0.0, 0.0};
+    real us[3] = {0.0, 0.0, 0.0};
     for (int cc = 0; cc < d; ++cc) us[cc] = u[cc * N + s];
-    double f = oracle_feq(q, a, rho[s], us, e);
+    real f = oracle_feq(q, a, rho[s], us, e);
     r += f;                                     /* Eq. (4) */
-    for (int cc = 0; cc < d; ++cc) m[cc] += e * (double)c[a][cc] * f;
+    for (int cc = 0; cc < d; ++cc) m[cc] += e * (real)c[a][cc] * f;
   }
   *rho_out = r;
   for (int cc = 0; cc < d; ++cc) {
@@ -273,9 +286,9 @@ static void update_node(const oracle_problem* p, double e, double dt,
 }
 
 /* One MacLAB step from (rho, u) into (rho_new, u_new). */
-static void step_once(const oracle_problem* p, double e, double dt,
-                      const double* rho, const double* u, double* rho_new,
-                      double* u_new) {
+static void step_once(const oracle_problem* p, real e, real dt,
+                      const real* rho, const real* u, real* rho_new,
+                      real* u_new) {
   const int d = lattice_dims(p->q);
   const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
   const int64_t N = nx * ny * nz;
@@ -289,7 +302,7 @@ static void step_once(const oracle_problem* p, double e, double dt,
           for (int cc = 0; cc < d; ++cc) u_new[cc * N + x] = u[cc * N + x];
           continue;
         }
-        double un[3];
+        real un[3];
         update_node(p, e, dt, rho, u, i, j, k, &rho_new[x], un);
         for (int cc = 0; cc < d; ++cc) u_new[cc * N + x] = un[cc];
       }
@@ -300,20 +313,20 @@ static void step_once(const oracle_problem* p, double e, double dt,
 /* One step evaluated only at the listed nodes (flat indices): rho_out[s] and
  * u_out[c * count + s] receive the values after the step. Fixed nodes keep
  * their values. For checking large lattices on a sample of nodes. */
-int oracle_step_at(const oracle_problem* p, const double* rho,
-                   const double* u, const int64_t* nodes, int64_t count,
-                   double* rho_out, double* u_out) {
+int oracle_step_at(const oracle_problem* p, const real* rho,
+                   const real* u, const int64_t* nodes, int64_t count,
+                   real* rho_out, real* u_out) {
   if (validate(p) || count < 0) return -1;
   const int d = lattice_dims(p->q);
   const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
   const int64_t N = nx * ny * nz;
-  const double e = oracle_particle_speed(p->nu, p->dx);
-  const double dt = p->dx / e;
+  const real e = oracle_particle_speed(p->nu, p->dx);
+  const real dt = p->dx / e;
   for (int64_t s = 0; s < count; ++s) {
     const int64_t x = nodes[s];
     if (x < 0 || x >= N) return -1;
     const int64_t i = x % nx, j = (x / nx) % ny, k = x / (nx * ny);
-    double un[3] = {0.0, 0.0, 0.0};
+    real un[3] = {0.0, 0.0, 0.0};
     const int f = fixed_face(p, i, j, k);
     if (f >= 0) {
       rho_out[s] = rho[x];
@@ -321,7 +334,7 @@ int oracle_step_at(const oracle_problem* p, const double* rho,
       if (p->face_kind[f] != ORACLE_FIXED) {
         /* the copied quantity is the new value at the nearest interior node */
         const int64_t t = interior_of(p, i, j, k);
-        double rt, ut[3] = {0.0, 0.0, 0.0};
+        real rt, ut[3] = {0.0, 0.0, 0.0};
         update_node(p, e, dt, rho, u, t % nx, (t / nx) % ny, t / (nx * ny), &rt, ut);
         if (p->face_kind[f] == ORACLE_RHO_NEUMANN)
           rho_out[s] = rt;
@@ -340,15 +353,15 @@ int oracle_step_at(const oracle_problem* p, const double* rho,
  * entries, u has d planes of N entries (component-major), x fastest.
  * Boundary values must already be in the arrays (oracle_impose_boundary).
  * Returns 0, or -1 on an invalid problem, -2 on allocation failure. */
-int oracle_run(const oracle_problem* p, double* rho, double* u,
+int oracle_run(const oracle_problem* p, real* rho, real* u,
                int64_t steps) {
   if (validate(p) || steps < 0) return -1;
   const int d = lattice_dims(p->q);
   const int64_t N = p->n[0] * p->n[1] * p->n[2];
-  const double e = oracle_particle_speed(p->nu, p->dx);
-  const double dt = p->dx / e;
-  double* r2 = (double*)malloc(sizeof(double) * (size_t)N);
-  double* u2 = (double*)malloc(sizeof(double) * (size_t)(N * d));
+  const real e = oracle_particle_speed(p->nu, p->dx);
+  const real dt = p->dx / e;
+  real* r2 = (real*)malloc(sizeof(real) * (size_t)N);
+  real* u2 = (real*)malloc(sizeof(real) * (size_t)(N * d));
   if (!r2 || !u2) {
     free(r2);
     free(u2);
@@ -356,8 +369,8 @@ int oracle_run(const oracle_problem* p, double* rho, double* u,
   }
   for (int64_t s = 0; s < steps; ++s) {
     step_once(p, e, dt, rho, u, r2, u2);
-    memcpy(rho, r2, sizeof(double) * (size_t)N);
-    memcpy(u, u2, sizeof(double) * (size_t)(N * d));
+    memcpy(rho, r2, sizeof(real) * (size_t)N);
+    memcpy(u, u2, sizeof(real) * (size_t)(N * d));
   }
   free(r2);
   free(u2);
@@ -371,11 +384,11 @@ int oracle_run(const oracle_problem* p, double* rho, double* u,
  * the paper's validity condition refers to), and the number of nodes holding
  * a non-finite value. Sums use Neumaier's compensated summation. */
 typedef struct {
-  double s, c;
+  real s, c;
 } neumaier;
 
-static void nsum_add(neumaier* a, double v) {
-  double t = a->s + v;
+static void nsum_add(neumaier* a, real v) {
+  real t = a->s + v;
   if (fabs(a->s) >= fabs(v))
     a->c += (a->s - t) + v;
   else
@@ -383,17 +396,17 @@ static void nsum_add(neumaier* a, double v) {
   a->s = t;
 }
 
-int oracle_diagnostics(const oracle_problem* p, const double* rho,
-                       const double* u, double* out7) {
+int oracle_diagnostics(const oracle_problem* p, const real* rho,
+                       const real* u, real* out7) {
   if (validate(p)) return -1;
   const int d = lattice_dims(p->q);
   const int64_t N = p->n[0] * p->n[1] * p->n[2];
-  const double e = oracle_particle_speed(p->nu, p->dx);
+  const real e = oracle_particle_speed(p->nu, p->dx);
   neumaier M = {0, 0}, P[3] = {{0, 0}, {0, 0}, {0, 0}}, E = {0, 0};
-  double umax = 0.0, bad = 0.0;
+  real umax = 0.0, bad = 0.0;
   for (int64_t x = 0; x < N; ++x) {
     int finite = isfinite(rho[x]);
-    double uu = 0.0;
+    real uu = 0.0;
     for (int c = 0; c < d; ++c) {
       finite = finite && isfinite(u[c * N + x]);
       uu += u[c * N + x] * u[c * N + x];
@@ -405,7 +418,7 @@ int oracle_diagnostics(const oracle_problem* p, const double* rho,
     nsum_add(&M, rho[x]);
     for (int c = 0; c < d; ++c) nsum_add(&P[c], rho[x] * u[c * N + x]);
     nsum_add(&E, 0.5 * rho[x] * uu);
-    double m = sqrt(uu) / e;
+    real m = sqrt(uu) / e;
     if (m > umax) umax = m;
   }
   out7[0] = M.s + M.c;
@@ -436,47 +449,47 @@ int oracle_diagnostics(const oracle_problem* p, const double* rho,
  * The whole trajectory is stored (steps + 1 states): for small problems only.
  * Outputs: grad_u0 (d planes of N), grad_G[3], loss[1]. Returns 0, -1 on an
  * invalid problem, -2 on allocation failure. */
-int oracle_adjoint_run(const oracle_problem* p, const double* rho0,
-                       const double* u0, int64_t steps,
-                       const double* u_target, double* grad_u0,
-                       double* grad_G, double* loss) {
+int oracle_adjoint_run(const oracle_problem* p, const real* rho0,
+                       const real* u0, int64_t steps,
+                       const real* u_target, real* grad_u0,
+                       real* grad_G, real* loss) {
   if (validate(p) || steps < 0) return -1;
   /* reverse mode covers periodic and fixed faces */
   for (int f = 0; f < 6; ++f)
     if (p->face_kind[f] == ORACLE_RHO_NEUMANN || p->face_kind[f] == ORACLE_PRESSURE) return -1;
   const int q = p->q, d = lattice_dims(q);
   const int(*c)[3] = lattice_c(q);
-  const double* w = lattice_w(q);
+  const real* w = lattice_w(q);
   const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
   const int64_t N = nx * ny * nz;
-  const double e = oracle_particle_speed(p->nu, p->dx);
-  const double dt = p->dx / e;
+  const real e = oracle_particle_speed(p->nu, p->dx);
+  const real dt = p->dx / e;
   const size_t S = (size_t)(N * (d + 1));
-  double* traj = (double*)malloc(sizeof(double) * S * (size_t)(steps + 1));
-  double* rb = (double*)malloc(sizeof(double) * (size_t)N);      /* rhobar */
-  double* ub = (double*)malloc(sizeof(double) * (size_t)(N * d)); /* ubar */
-  double* rt = (double*)malloc(sizeof(double) * (size_t)N);      /* rbar_tot */
-  double* mb = (double*)malloc(sizeof(double) * (size_t)(N * d)); /* mbar */
+  real* traj = (real*)malloc(sizeof(real) * S * (size_t)(steps + 1));
+  real* rb = (real*)malloc(sizeof(real) * (size_t)N);      /* rhobar */
+  real* ub = (real*)malloc(sizeof(real) * (size_t)(N * d)); /* ubar */
+  real* rt = (real*)malloc(sizeof(real) * (size_t)N);      /* rbar_tot */
+  real* mb = (real*)malloc(sizeof(real) * (size_t)(N * d)); /* mbar */
   if (!traj || !rb || !ub || !rt || !mb) {
     free(traj); free(rb); free(ub); free(rt); free(mb);
     return -2;
   }
   /* forward, keeping every state: state n = [rho (N) | u (d N)] */
-  memcpy(traj, rho0, sizeof(double) * (size_t)N);
-  memcpy(traj + N, u0, sizeof(double) * (size_t)(N * d));
+  memcpy(traj, rho0, sizeof(real) * (size_t)N);
+  memcpy(traj + N, u0, sizeof(real) * (size_t)(N * d));
   oracle_impose_boundary(p, traj, traj + N);
   for (int64_t s = 0; s < steps; ++s) {
-    double* cur = traj + S * (size_t)s;
-    double* nxt = traj + S * (size_t)(s + 1);
+    real* cur = traj + S * (size_t)s;
+    real* nxt = traj + S * (size_t)(s + 1);
     step_once(p, e, dt, cur, cur + N, nxt, nxt + N);
   }
   /* loss and its derivative with respect to the final velocity */
-  const double* fin = traj + S * (size_t)steps;
-  double L = 0.0;
+  const real* fin = traj + S * (size_t)steps;
+  real L = 0.0;
   for (int64_t x = 0; x < N; ++x) {
     rb[x] = 0.0;
     for (int cc = 0; cc < d; ++cc) {
-      double diff = fin[N + cc * N + x] - u_target[cc * N + x];
+      real diff = fin[N + cc * N + x] - u_target[cc * N + x];
       L += diff * diff;
       ub[cc * N + x] = 2.0 * diff;
     }
@@ -484,8 +497,8 @@ int oracle_adjoint_run(const oracle_problem* p, const double* rho0,
   *loss = L;
   for (int cc = 0; cc < 3; ++cc) grad_G[cc] = 0.0;
   for (int64_t s = steps - 1; s >= 0; --s) {
-    const double* cur = traj + S * (size_t)s;       /* state n     */
-    const double* nxt = traj + S * (size_t)(s + 1); /* state n + 1 */
+    const real* cur = traj + S * (size_t)s;       /* state n     */
+    const real* nxt = traj + S * (size_t)(s + 1); /* state n + 1 */
     /* through u' = m' / rho' */
     for (int64_t k = 0; k < nz; ++k)
       for (int64_t j = 0; j < ny; ++j)
@@ -496,7 +509,7 @@ int oracle_adjoint_run(const oracle_problem* p, const double* rho0,
             for (int cc = 0; cc < d; ++cc) mb[cc * N + x] = 0.0;
             continue;
           }
-          double r1 = nxt[x], dot = 0.0;
+          real r1 = nxt[x], dot = 0.0;
           for (int cc = 0; cc < d; ++cc) {
             mb[cc * N + x] = ub[cc * N + x] / r1;
             dot += ub[cc * N + x] * nxt[N + cc * N + x];
@@ -509,23 +522,23 @@ int oracle_adjoint_run(const oracle_problem* p, const double* rho0,
       for (int64_t j = 0; j < ny; ++j)
         for (int64_t i = 0; i < nx; ++i) {
           const int64_t y = i + nx * (j + ny * k);
-          double rho = cur[y];
-          double uu[3] = {0.0, 0.0, 0.0};
+          real rho = cur[y];
+          real uu[3] = {0.0, 0.0, 0.0};
           for (int cc = 0; cc < d; ++cc) uu[cc] = cur[N + cc * N + y];
-          double rbar = 0.0, ubar[3] = {0.0, 0.0, 0.0};
+          real rbar = 0.0, ubar[3] = {0.0, 0.0, 0.0};
           for (int a = 0; a < q; ++a) {
             int64_t xi = wrap(i + c[a][0], nx);
             int64_t xj = wrap(j + c[a][1], ny);
             int64_t xk = wrap(k + c[a][2], nz);
             int64_t x = xi + nx * (xj + ny * xk);
-            double fbar = rt[x];
-            for (int cc = 0; cc < d; ++cc) fbar += e * (double)c[a][cc] * mb[cc * N + x];
-            double f = oracle_feq(q, a, rho, uu, e);
+            real fbar = rt[x];
+            for (int cc = 0; cc < d; ++cc) fbar += e * (real)c[a][cc] * mb[cc * N + x];
+            real f = oracle_feq(q, a, rho, uu, e);
             rbar += fbar * f / rho;
-            double eu = 0.0;
-            for (int cc = 0; cc < d; ++cc) eu += e * (double)c[a][cc] * uu[cc];
+            real eu = 0.0;
+            for (int cc = 0; cc < d; ++cc) eu += e * (real)c[a][cc] * uu[cc];
             for (int cc = 0; cc < d; ++cc) {
-              double ea = e * (double)c[a][cc];
+              real ea = e * (real)c[a][cc];
               ubar[cc] += fbar * w[a] * rho *
                           (3.0 * ea / (e * e) + 9.0 * eu * ea / (e * e * e * e) -
                            3.0 * uu[cc] / (e * e));
@@ -539,7 +552,7 @@ int oracle_adjoint_run(const oracle_problem* p, const double* rho0,
           for (int cc = 0; cc < d; ++cc) ub[cc * N + y] = ubar[cc];
         }
   }
-  memcpy(grad_u0, ub, sizeof(double) * (size_t)(N * d));
+  memcpy(grad_u0, ub, sizeof(real) * (size_t)(N * d));
   free(traj); free(rb); free(ub); free(rt); free(mb);
   return 0;
 }

@@ -29,11 +29,13 @@ their results are stored in compact form:
   in the loss adds a part that grows as 1/h). Two directions (the smallest
   |derivative| in u0 and in G) are also differenced at h = 1e-5 and 1e-6, to
   show the rounding floor that rules out the smaller steps.
+* ``cavity1024_re1000_ext.npz`` -- the same cavity and checkpoints with the
+  oracle built in x87 extended precision (oracle.run_extended).
 * ``batch512_stable.npz`` -- the three largest cavities of the 512-cavity
   draw (seed 4) whose lattice Reynolds number U dx / nu is at most 2.5,
   2000 steps each: diagnostics and every 4th node per axis of rho and u.
 
-Usage: python tests/golden/make_references.py {cube64,cube64_re400,cavity1024,adjoint512 [workers],batch512}
+Usage: python tests/golden/make_references.py {cube64,cube64_re400,cavity1024,cavity1024_extended,adjoint512 [workers],batch512}
 """
 from __future__ import annotations
 
@@ -134,6 +136,51 @@ def cavity1024(resume=None):
         print(f"cavity1024: {target} steps after {time.time() - t0:.0f} s", flush=True)
 
 
+def cavity1024_extended(resume=None, targets=(1000, 5000, 20000, 50000)):
+    """The 1024^2 cavity of cavity1024() with the oracle built in x87
+    extended precision (run_extended): the same checkpoints, written to
+    cavity1024_re1000_ext.npz as float64 after each target is reached (the
+    state itself stays in extended precision between chunks; `resume` keeps
+    it on disk so an interrupted run continues)."""
+    import tempfile
+
+    resume = resume or os.path.join(tempfile.gettempdir(), "maclab_cavity1024_ext_state.npz")
+    case = workloads.cavity_2d(n=1024, Re=1000.0, U=0.1)
+    p = problem(case)
+    rho, u, done, elapsed, out = case.rho, case.u, 0, 0.0, {}
+    if os.path.exists(resume):
+        z = np.load(resume)
+        rho, u = z["rho"].view(np.longdouble).reshape(case.rho.shape), z["u"].view(np.longdouble).reshape(case.u.shape)
+        done, elapsed = int(z["done"]), float(z["elapsed"])
+        out = {k[4:]: z[k] for k in z.files if k.startswith("out_")}
+        print(f"cavity1024_extended: resuming at step {done}", flush=True)
+    t0 = time.time() - elapsed
+
+    def save_state():
+        np.savez(resume, rho=np.asarray(rho, dtype=np.longdouble).view(np.uint8), u=np.asarray(u, dtype=np.longdouble).view(np.uint8),
+                 done=done, elapsed=time.time() - t0, **{"out_" + k: v for k, v in out.items()})
+
+    c = case.n[0] // 2
+    for target in targets:
+        while done < target:
+            n = min(1000, target - done)
+            rho, u = oracle.run_extended(p, rho, u, n)
+            done += n
+            save_state()
+            print(f"cavity1024_extended: {done} steps after {time.time() - t0:.0f} s", flush=True)
+        if f"u_sub_{target}" in out:
+            continue
+        r64, u64 = rho.astype(np.float64), u.astype(np.float64)
+        out[f"diag_{target}"] = oracle.diagnostics(p, r64, u64)
+        out[f"ux_centre_{target}"] = 0.5 * (u64[0, 0, :, c - 1] + u64[0, 0, :, c])
+        out[f"uy_centre_{target}"] = 0.5 * (u64[1, 0, c - 1, :] + u64[1, 0, c, :])
+        out[f"rho_sub_{target}"] = r64[0, ::16, ::16]
+        out[f"u_sub_{target}"] = u64[:, 0, ::16, ::16]
+        out[f"seconds_{target}"] = time.time() - t0
+        np.savez_compressed(os.path.join(HERE, "cavity1024_re1000_ext.npz"), stride=16, **out)
+        save_state()
+
+
 def _loss(args):
     which, k, sign, h = args
     case, tgt = workloads.adjoint_case()
@@ -211,5 +258,7 @@ if __name__ == "__main__":
         adjoint512(int(sys.argv[2]) if len(sys.argv) > 2 else 6)
     elif sys.argv[1] == "batch512":
         batch512()
+    elif sys.argv[1] == "cavity1024_extended":
+        cavity1024_extended()
     else:
         {"cube64": cube64, "cube64_re400": cube64_re400, "cavity1024": cavity1024}[sys.argv[1]]()

@@ -4,7 +4,8 @@ density held, velocity from that node) against the FP64 oracle, on the
 general kernel and on the fast D2Q9 and D3Q19 kernels, in every storage.
 
 Tolerances as for the step: FP64 1e-12, FP32 1e-5, HILO / S16 2e-3 relative
-L2 of u and rho over all nodes."""
+L2 of u and rho over all nodes; FP64 against the oracle built in extended
+precision (see `reference`)."""
 import ctypes
 
 import numpy as np
@@ -17,6 +18,21 @@ from conftest import rel_l2, to_problem
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-12, "fp32": 1e-5, "hilo": 2e-3, "s16": 2e-3}
+
+
+def reference(case, steps, precision):
+    """The oracle's run. FP64 storage is compared with the oracle built in
+    extended precision: these flows are slow (|u~| down to 1e-4), and the
+    FP64 oracle's own rounding of O(1) population sums, about 1e-16
+    absolute per step, is then already 1e-11 relative to u after a few
+    thousand steps."""
+    p = to_problem(case)
+    if precision == "fp64":
+        r, u = oracle.run_extended(p, case.rho, case.u, steps)
+        r64, u64 = oracle.run(p, case.rho, case.u, steps)
+        print(f"  (FP64 oracle vs extended: relL2 u {rel_l2(u64, u.astype(np.float64)):.2e})", flush=True)
+        return r.astype(np.float64), u.astype(np.float64)
+    return oracle.run(p, case.rho, case.u, steps)
 
 
 def make_sim(case, precision, kernel=None):
@@ -91,7 +107,7 @@ def test_faces_against_oracle(name, mk, steps, fast, kernel, precision):
     assert sim.tiling()["kernel"] == want
     sim.step(steps)
     rho, u = sim.fields()
-    orho, ou = oracle.run(to_problem(case), case.rho, case.u, steps)
+    orho, ou = reference(case, steps, precision)
     eu, er = rel_l2(u, ou), rel_l2(rho, orho)
     print(f"  relL2 u {eu:.2e} rho {er:.2e}", flush=True)
     assert eu < TOL[precision] and er < TOL[precision]
@@ -111,7 +127,7 @@ def test_pressure_driven_channel_reaches_poiseuille_on_the_gpu():
     local = e * e / 3.0 * (rho[0, m + 1, c] - rho[0, m - 1, c]) / (2.0 * case.dx)
     prof = 1.0 / (2.0 * rho[0, m, c] * case.nu) * local * (xx * xx - h * xx)
     err = float(np.abs(u[1, 0, m, :] - prof).max() / np.abs(prof).max())
-    orho, ou = oracle.run(to_problem(case), case.rho, case.u, steps)
+    orho, ou = reference(case, steps, "fp64")
     print(f"  steady after {steps} steps (residual {r}); Eq. (8) at mid-channel {err:.2e}; "
           f"vs oracle {rel_l2(u, ou):.2e}", flush=True)
     assert err < 1e-6

@@ -134,3 +134,42 @@ def test_cavity1024_against_stored_oracle(precision):
         for got, want in ((0.5 * (u[0, 0, :, c - 1] + u[0, 0, :, c]), ref[f"ux_centre_{m}"]),
                           (0.5 * (u[1, 0, c - 1, :] + u[1, 0, c, :]), ref[f"uy_centre_{m}"])):
             assert np.sqrt(np.mean((got - want) ** 2)) / U < tol
+
+
+def _ext_checkpoints():
+    path = os.path.join(GOLD, "cavity1024_re1000_ext.npz")
+    if not os.path.exists(path):
+        return []
+    z = np.load(path)
+    return sorted(int(k.split("_")[2]) for k in z.files if k.startswith("u_sub_"))
+
+
+@pytest.mark.slow
+def test_cavity1024_fp64_against_extended_oracle():
+    """The 1024^2 cavity in FP64 against the oracle built in extended
+    precision (tests/golden/cavity1024_re1000_ext.npz), at the flat bar of
+    1e-12 relative L2 at every stored checkpoint. The FP64 oracle itself
+    differs from the extended one by its own rounding (printed), which is
+    what the sqrt(steps) bar of test_cavity1024_against_stored_oracle
+    allows for."""
+    marks = _ext_checkpoints()
+    if not marks:
+        pytest.skip("extended cavity reference not generated")
+    ext = np.load(os.path.join(GOLD, "cavity1024_re1000_ext.npz"))
+    f64 = np.load(os.path.join(GOLD, "cavity1024_re1000.npz")) if _cavity_checkpoints() else None
+    case = workloads.cavity_2d(n=1024, Re=1000.0, U=0.1)
+    sim = _sim(case, "fp64")
+    done = 0
+    s = int(ext["stride"])
+    for m in marks:
+        print(f"[ref] cavity1024 fp64 to step {m} (extended oracle)", flush=True)
+        sim.step(m - done)
+        done = m
+        rho, u = sim.fields()
+        eu = rel_l2(u[:, 0, ::s, ::s], ext[f"u_sub_{m}"])
+        er = rel_l2(rho[0, ::s, ::s], ext[f"rho_sub_{m}"])
+        line = f"  step {m}: GPU FP64 vs extended oracle relL2 u={eu:.2e} rho={er:.2e}"
+        if f64 is not None and f"u_sub_{m}" in f64.files:
+            line += f"; FP64 oracle vs extended u={rel_l2(f64[f'u_sub_{m}'], ext[f'u_sub_{m}']):.2e}"
+        print(line, flush=True)
+        assert eu < 1e-12 and er < 1e-12

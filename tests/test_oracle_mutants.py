@@ -17,12 +17,12 @@ MUTANTS = {
     "isotropic_coeff": ("- 1.5 * uu / e2", "- 1.0 * uu / e2"),
     "linear_scale": ("3.0 * eu / e2", "3.0 * eu / e"),
     "push_not_pull": ("int64_t si = wrap(i - c[a][0], nx);", "int64_t si = wrap(i + c[a][0], nx);"),
-    "momentum_component": ("m[cc] += e * (double)c[a][cc] * f;", "m[cc] += e * (double)c[a][(cc + 1) % d] * f;"),
+    "momentum_component": ("m[cc] += e * (real)c[a][cc] * f;", "m[cc] += e * (real)c[a][(cc + 1) % d] * f;"),
     "force_sign": ("m[cc] / r + dt * p->G[cc] / r", "m[cc] / r - dt * p->G[cc] / r"),
     "old_density": ("m[cc] / r + dt", "m[cc] / rho[i + nx * (j + ny * k)] + dt"),
-    "viscosity_map": ("return 6.0 * nu / dx;", "return 3.0 * nu / dx;"),
-    "d3q19_weight": ("1.0 / 18.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,\n    1.0 / 36.0, 1.0 / 36.0",
-                     "1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,\n    1.0 / 36.0, 1.0 / 36.0"),
+    "viscosity_map": ("return 6.0 * (real)nu / (real)dx;", "return 3.0 * (real)nu / (real)dx;"),
+    "d3q19_weight": ("(real)1 / 18, (real)1 / 36, (real)1 / 36, (real)1 / 36,\n    (real)1 / 36, (real)1 / 36",
+                     "(real)1 / 36, (real)1 / 36, (real)1 / 36, (real)1 / 36,\n    (real)1 / 36, (real)1 / 36"),
     "d3q19_velocity": ("{-1, 0, 1}, {1, 0, -1}}", "{1, 0, 1}, {1, 0, -1}}"),
     "d2q9_velocity": ("{1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}}", "{1, 1, 0}, {-1, 1, 0}, {1, -1, 0}, {-1, -1, 0}}"),
     "corner_owner": ("for (int f = 0; f < 6; ++f) {\n    if (p->face_kind[f] == ORACLE_PERIODIC) continue;",

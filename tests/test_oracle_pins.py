@@ -667,3 +667,51 @@ def test_derived_faces_copy_the_nearest_interior_node(oracle_lib, q):
         nodes = np.arange(case.n[0] * case.n[1] * case.n[2])
         ro, uo = oracle.step_at(p, r0.ravel(), u0.reshape(case.d, -1), nodes)
         assert np.array_equal(ro, rho.ravel()) and np.array_equal(uo, u.reshape(case.d, -1))
+
+
+# ------------------------------------------ the extended-precision build
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_extended_build_is_the_same_scheme_with_smaller_rounding(oracle_lib, q):
+    """The oracle built with x87 extended precision. Any unidirectional
+    periodic shear flow u_x(y) with rho = 1 is advanced exactly by the
+    three-point stencil u_j <- (2 u_j + (u_(j-1) + u_(j+1)) / 2) / 3 (the
+    exact shear-wave result behind the factor (2 + cos(2 pi m / N)) / 3):
+    the extended build follows it to its own rounding, more than a thousand
+    times closer than the FP64 oracle, and on a random state it agrees with
+    the FP64 oracle to the FP64 rounding."""
+    n, steps = 32, 7
+    case = workloads.shear_wave(q, n, 3, 0.2)
+    prof = np.random.default_rng(5).standard_normal(n) * 0.05 * oracle.particle_speed(case.nu, case.dx)
+    case.u[0] = prof[None, :, None]
+    ref = prof.astype(np.longdouble)
+    for _ in range(steps):
+        ref = (2 * ref + (np.roll(ref, 1) + np.roll(ref, -1)) / 2) / 3
+    rho, u = oracle.run_extended(to_problem(case), case.rho, case.u, steps)
+    _, u64 = _run(case, steps)
+    err_ext = float(np.abs(u[0] - ref[None, :, None]).max())
+    err_64 = float(np.abs(u64[0] - ref[None, :, None]).max())
+    e = oracle.particle_speed(case.nu, case.dx)
+    print(f"shear flow error: extended {err_ext:.2e}, FP64 {err_64:.2e} (e = {e:.3f})")
+    assert err_ext < 2e-19 * e
+    assert float(np.abs(rho - 1).max()) < 1e-18
+    assert float(np.abs(u[1:]).max()) < 1e-18
+    assert err_ext < err_64 / 1000
+    rnd = workloads.random_field(q, (9, 8, 5) if q == 19 else (13, 11, 1), seed=61)
+    rnd.G = (0.2, -0.1, 0.05)
+    r64, v64 = _run(rnd, 20)
+    rx, vx = oracle.run_extended(to_problem(rnd), rnd.rho, rnd.u, 20)
+    assert rel_l2(v64, vx.astype(np.float64)) < 1e-13
+    assert rel_l2(r64, rx.astype(np.float64)) < 1e-14
+
+
+def test_extended_build_keeps_the_couette_profile(oracle_lib):
+    """Test 1's linear profile is a steady state of the extended build too,
+    to its rounding."""
+    case = workloads.channel(nu=0.001, u0=0.1)
+    prof = workloads.channel_profile(case, 0.1, 0.0)
+    case.u[0] = prof[None, :, None]
+    rho, u = oracle.run_extended(to_problem(case), case.rho, case.u, 200)
+    e = oracle.particle_speed(case.nu, case.dx)
+    assert float(np.abs(u[0, 0] - prof[:, None]).max()) < 200 * 1.1e-19 * e * 4
+    assert float(np.abs(rho - 1).max()) < 200 * 1.1e-19 * 4
