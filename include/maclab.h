@@ -147,6 +147,21 @@ int maclab_get_fields(maclab_t h, double* rho, double* u, int on_device);
  * Deterministic (fixed reduction order). Synchronises. */
 int maclab_diagnostics(maclab_t h, double out[7]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * reductions of maclab_diagnostics, enqueued on the handle's stream, with
+ * the 7 doubles written to caller device memory out_dev (same order and
+ * values) and without synchronising. Its reduction partials live in a fixed
+ * 65.6 KB device array of the library (one per device, held until the
+ * process ends, its address looked up when the first handle on the device
+ * is created), not in the workspace; it calls no allocating routine. Every
+ * call on one device shares that array: calls that overlap in time on one
+ * device (different streams or threads) race and must be ordered by the
+ * caller. MACLAB_EWORKSPACE if a reduction would not fit the array (cannot
+ * happen with the library's fixed reduction width), MACLAB_EHIP if the
+ * array's address cannot be obtained. */
+int maclab_diagnostics_noalloc(maclab_t h, double* out_dev);
+
 /* Host out[6]: particle speed e, time step dt, lattice Reynolds number
  * R_le = max_fixed |u_b| dx / nu (main text, stability remark after
  * Eq. (6)), Mach number R_le / 6, steps taken, simulated time steps * dt. */

@@ -16,7 +16,8 @@ PERIODIC, FIXED, RHO_NEUMANN, PRESSURE = 0, 1, 2, 3
 # Exported symbols, in the order include/maclab.h declares them.
 SYMBOLS = (
     "maclab_workspace_bytes", "maclab_init", "maclab_set_bc", "maclab_set_fields", "maclab_step",
-    "maclab_step_checked", "maclab_get_fields", "maclab_diagnostics", "maclab_params",
+    "maclab_step_checked", "maclab_get_fields", "maclab_diagnostics", "maclab_diagnostics_noalloc",
+    "maclab_params",
     "maclab_state_bytes", "maclab_save_state", "maclab_load_state", "maclab_get_tiling",
     "maclab_set_tiling", "maclab_autotune", "maclab_set_body_force", "maclab_step_external",
     "maclab_adjoint_bytes", "maclab_adjoint_seed", "maclab_adjoint_reset", "maclab_adjoint_step",
@@ -76,6 +77,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.maclab_step_checked.argtypes = [H, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     lib.maclab_get_fields.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     lib.maclab_diagnostics.argtypes = [H, dp]
+    lib.maclab_diagnostics_noalloc.argtypes = [H, ctypes.c_void_p]
     lib.maclab_params.argtypes = [H, dp]
     lib.maclab_state_bytes.restype = ctypes.c_size_t
     lib.maclab_state_bytes.argtypes = [H]

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -39,6 +40,7 @@ struct maclab_s {
   double e = 0, dt = 0;
   int64_t steps = 0;
   int cus = 256;               // compute units of the device
+  int device = 0;              // HIP device the handle was created on
   Plan plan;                   // kernel and tiling of the step
   bool plan_set = false;       // chosen by maclab_set_tiling / maclab_autotune
   int adj_kernel = -1;         // reverse step: -1 automatic, 0 general, 3 fast D2Q9
@@ -50,6 +52,40 @@ struct maclab_s {
 namespace {
 
 thread_local std::string g_err;
+
+// ------------------------------------------------ allocation-free scratch
+// The reduction partials and result of maclab_diagnostics_noalloc live in
+// this fixed device array instead of the caller's workspace: (kDiagBlocks +
+// 1) rows of kDiagValues doubles, 65.6 KB on every device the library runs
+// on, held until the process ends. In host code `scratch` names a host-side
+// stand-in, not device memory: host code uses only the per-device address
+// that hipGetSymbolAddress returns (device_scratch).
+constexpr size_t kScratchDoubles = (size_t)(kDiagBlocks + 1) * kDiagValues;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Looks up (once per device, with that device current) the device address
+// of `scratch`; returns the HIP status of the lookup.
+hipError_t device_scratch(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 constexpr size_t kAlign = 256;
 constexpr size_t kStagingMax = size_t(8) << 20;
@@ -312,9 +348,15 @@ int maclab_init(const maclab_config* cfg, maclab_t* out) {
   }
   {
     int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-      h->cus = cus;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      h->device = dev;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        h->cus = cus;
+      // the address of the allocation-free entry points' scratch array on
+      // this device (once per device; the entry point reports a failure)
+      double* unused = nullptr;
+      (void)device_scratch(dev, &unused);
+    }
   }
   h->e = 6.0 * cfg->nu / cfg->dx;  // Eq. (6)
   h->dt = cfg->dx / h->e;          // text after Eq. (6)
@@ -407,6 +449,25 @@ int maclab_diagnostics(maclab_t h, double out[7]) {
   HIP_TRY(h, hipMemcpyAsync(r, h->result, sizeof r, hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   for (int i = 0; i < 7; ++i) out[i] = r[i];
+  return MACLAB_OK;
+}
+
+int maclab_diagnostics_noalloc(maclab_t h, double* out_dev) {
+  if (!h) return fail(nullptr, MACLAB_EINVAL, "handle is NULL");
+  if (!out_dev) return fail(h, MACLAB_EINVAL, "out_dev is NULL");
+  // the reduction writes one row of partials per workgroup (at most
+  // kDiagBlocks), then a result row; all of it must fit the scratch array
+  const int64_t want = (h->L.N + 255) / 256;
+  const int64_t rows = std::min<int64_t>(std::max<int64_t>(want, 1), kDiagBlocks) + 1;
+  if ((size_t)rows * kDiagValues > kScratchDoubles)
+    return fail(h, MACLAB_EWORKSPACE, "diagnostics need %lld scratch doubles, the array holds %zu",
+                (long long)rows * kDiagValues, kScratchDoubles);
+  double* base = nullptr;
+  HIP_TRY(h, device_scratch(h->device, &base));
+  double* partials = base;
+  double* result = base + (size_t)kDiagBlocks * kDiagValues;
+  HIP_TRY(h, launch_diagnostics(h->L, h->state[h->cur], h->cfg.rho_ref, h->e, partials, result, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(out_dev, result, 7 * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   return MACLAB_OK;
 }
 
@@ -846,6 +907,7 @@ struct maclab_batch_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int cus = 256;
+  int device = 0;
   std::string err;
 };
 
@@ -1073,9 +1135,13 @@ int maclab_batch_init(const maclab_config* cfgs, int count, void* workspace, siz
   b->table = (Lattice2D*)(shared + B.partial + B.staging + B.adjoint);
   b->items = (int4*)((char*)b->table + B.table);
   int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) == hipSuccess &&
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-    b->cus = cus;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    b->device = dev;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      b->cus = cus;
+    double* unused = nullptr;
+    (void)device_scratch(dev, &unused);
+  }
   b->lat.reserve(count);
   b->base.resize(count);
   const int bytes = B.L[0].bytes;
@@ -1104,6 +1170,7 @@ int maclab_batch_init(const maclab_config* cfgs, int count, void* workspace, siz
       for (int c = 0; c < 3; ++c) h->fv.u[f][c] = 0.0;
     }
     h->cus = b->cus;
+    h->device = b->device;
     h->e = 6.0 * cfgs[i].nu / cfgs[i].dx;  // Eq. (6)
     h->dt = cfgs[i].dx / h->e;
     b->lat.push_back(h);
