@@ -217,21 +217,24 @@ __device__ __forceinline__ T div36(T x) {
 
 // ------------------------------------------------------ cross-lane moves
 // DPP wave rotates: lane l receives the value of lane l-1 (lane 0 that of
-// lane 63), or of lane l+1 (lane 63 that of lane 0).
+// lane 63), or of lane l+1 (lane 63 that of lane 0). A rotate gives every
+// lane a source, so bound_ctrl (zero for lanes without one) changes no value;
+// set, it lets the compiler drop the unused "old" operand (a register move
+// per rotate where the result cannot be folded into the instruction using it).
 __device__ __forceinline__ float dpp_from_left(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x13C, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x13C, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float dpp_from_right(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xF, 0xF, true));
 }
 __device__ __forceinline__ double dpp_from_left(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) & 0xffffffff), 0x13C, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) >> 32), 0x13C, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) & 0xffffffff), 0x13C, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) >> 32), 0x13C, 0xF, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ double dpp_from_right(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) & 0xffffffff), 0x134, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) >> 32), 0x134, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) & 0xffffffff), 0x134, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) >> 32), 0x134, 0xF, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 

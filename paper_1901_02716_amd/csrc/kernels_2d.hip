@@ -5,12 +5,13 @@
 //    one item: lane l holds the KX consecutive nodes x0 + KX*l .. + KX-1 of
 //    the segment (64*KX nodes wide) and the wavefront marches up the rows of
 //    its band, keeping three rolling row accumulators (rows y-1, y, y+1).
-//  - Each node computes the equilibria of its 9 links once (Eq. (2) in the
-//    deviation form F^_a = f_eq_a - w_a rho_ref, times 36) and pushes them to
-//    x + c_a: the y shift is the rolling accumulator, the x shift an in-lane
-//    move or a DPP wave rotate across lanes. At the edges of a segment that
-//    does not span the whole row, the two lanes at the edges also evaluate
-//    the links of the neighbouring node outside the segment.
+//  - The weights are a tensor product (36 w = 6 w_x 6 w_y), so each node
+//    computes the six moments of its equilibrium (Eq. (2), deviation form,
+//    times 36) and the gather runs as an x pass (three values sent to each
+//    x neighbour: an in-lane move or a DPP wave rotate across lanes) and a
+//    y pass (the rolling row accumulators); see moments2 / send2. At the
+//    edges of a segment that does not span the whole row, the two lanes at
+//    the edges also take the moments of the node just outside it.
 //  - After source row y is pushed, destination row y-1 holds the gathers of
 //    Eqs. (4)-(5): rho' = rho_ref + drho', u~' = (m' + g) / rho'.
 //  - There is no LDS and no barrier; every wavefront works alone.
@@ -33,36 +34,61 @@ struct Fast2DParams {
   uint32_t sr_key;
 };
 
+// The D2Q9 weights are a tensor product, 36 w_a = (6 w_x(c_x)) (6 w_y(c_y))
+// with 6 w(0) = 4 and 6 w(+-1) = 1, and the link values of Eq. (2) in the
+// deviation form F^_a = f_eq_a - w_a rho_ref are, times 36,
+//   36 F^_a = (6 w_x)(6 w_y) [a + c_x bx + c_y by + 1.5 (c_x^2 cxx + c_y^2 cyy) + 3 c_x c_y cxy]
+// with rho = rho_ref + drho, bx = 3 rho u_x, by = 3 rho u_y, cxx = bx u_x,
+// cyy = by u_y, cxy = bx u_y and a = drho - (cxx + cyy) / 2. So the gather of
+// Eqs. (4)-(5) runs as a pass along x and a pass along y over the six
+// moments of each node instead of over its nine links. Along x, node x
+// receives from x-1 and x+1 (c_x = +1 from the left, -1 from the right)
+//   R0 = a + bx + 1.5 cxx,  R1 = by + 3 cxy,  R2 = cyy   (sent to the right)
+//   L0 = a - bx + 1.5 cxx,  L1 = by - 3 cxy,  L2 = cyy   (sent to the left)
+// and forms, per power of c_y, the x-gathered density (T) and x momentum (U)
+// terms of its row:
+//   T0 = 4 a + R0' + L0',  T1 = 4 by + R1' + L1',  T2 = 1.5 (4 cyy + R2' + L2')
+//   U0 = R0' - L0',        U1 = R1' - L1',         U2 = 1.5 (R2' - L2').
+// Along y the row above receives T0 + T1 + T2 (density and y momentum) and
+// U0 + U1 + U2 (x momentum), the row below T0 - T1 + T2 (density, minus y
+// momentum) and U0 - U1 + U2, and the row itself 4 T0 and 4 U0: together
+// 36 drho' and 36 m' of Eqs. (4)-(5).
 template <class T>
-struct Links2 {
-  T f0, qxp, qxm, qyp, qym;  // rest, and the axis links divided by 4
-  T pp, mm, pm, mp;          // (1,1) (-1,-1) (1,-1) (-1,1)
+struct Mom2 {
+  T a, bx, by, cxx, cyy, cxy;
 };
 
-// The 9 link values of one node, times 36: 36 F^_a = wnum_a [a + c.b +
-// sum_i c_i^2 q_ii + c_x c_y q_xy] with a = drho - 1.5 rho |u|^2, b = 3 rho u,
-// q_ii = 4.5 rho u_i^2, q_xy = 9 rho u_x u_y (wnum = 16, 4, 1).
 template <class T>
-__device__ __forceinline__ void links2(T dr, T ux, T uy, T rho_ref, Links2<T>& L) {
+__device__ __forceinline__ void moments2(T dr, T ux, T uy, T rho_ref, Mom2<T>& M) {
 #pragma clang fp contract(off)
   const T rho = rho_ref + dr;
   const T r3 = (T)3 * rho;
-  const T bx = r3 * ux, by = r3 * uy;
-  const T cxx = bx * ux, cyy = by * uy, cxy = bx * uy;  // 3 rho u_i u_j
-  const T a = fma_t(cxx + cyy, (T)-0.5, dr);
-  const T sx = fma_t(cxx, (T)1.5, a), sy = fma_t(cyy, (T)1.5, a);
-  L.f0 = (T)16 * a;
-  L.qxp = sx + bx;
-  L.qxm = sx - bx;
-  L.qyp = sy + by;
-  L.qym = sy - by;
-  const T t = fma_t(cyy, (T)1.5, sx);
-  const T p = fma_t(cxy, (T)3, t), m = fma_t(cxy, (T)-3, t);
-  const T u = bx + by, v = bx - by;
-  L.pp = p + u;
-  L.mm = p - u;
-  L.pm = m + v;
-  L.mp = m - v;
+  M.bx = r3 * ux;
+  M.by = r3 * uy;
+  M.cxx = M.bx * ux;
+  M.cyy = M.by * uy;
+  M.cxy = M.bx * uy;
+  M.a = fma_t(M.cxx + M.cyy, (T)-0.5, dr);
+}
+
+// What a node sends along x: to the right (R0, R1; R2 = cyy) and to the
+// left (L0, L1; L2 = cyy).
+template <class T>
+struct Send2 {
+  T r0, r1, l0, l1, c2;
+};
+
+template <class T>
+__device__ __forceinline__ Send2<T> send2(const Mom2<T>& M) {
+#pragma clang fp contract(off)
+  Send2<T> S;
+  const T s = fma_t(M.cxx, (T)1.5, M.a);
+  S.r0 = s + M.bx;
+  S.l0 = s - M.bx;
+  S.r1 = fma_t(M.cxy, (T)3, M.by);
+  S.l1 = fma_t(M.cxy, (T)-3, M.by);
+  S.c2 = M.cyy;
+  return S;
 }
 
 template <class E, int KX>
@@ -147,11 +173,12 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src, typename C::elem* 
   const bool halo_lane = (lane == 0 && need_left) || (lane == 63 && need_right);
   auto ywrap = [&](int y) { return lt.yper ? (y + lt.ny) % lt.ny : y; };
 
-  // raw rows: a ring of three rows in flight (row y in slot (y - y0 + 1) mod
-  // 3), the source row being pushed (cur) and the row before it (prev, whose
-  // wall nodes are stored back unchanged)
-  V ring[3][3], cur[3], prev[3];
-  E hring[3][3];
+  // raw rows: a ring of five slots, row y in slot (y - y0 + 1) mod 5: the
+  // source row being pushed, the row before it (whose wall nodes are stored
+  // back unchanged) and three rows in flight. Slots are chosen at compile
+  // time, so no row is copied between registers.
+  V ring[5][3];
+  E hring[5][3];
   auto load_row = [&](int y, bool valid, V (&ld)[3], E (&hld)[3]) {
     const int rb = (int)((int64_t)lt.pitch * ywrap(y) * EB);
     const int off = valid && in_row ? rb + xl * EB : kOutOfRange;
@@ -172,78 +199,68 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src, typename C::elem* 
   // Destination node d needs its own links (rest, +-y), the +x-moving links
   // of node d-1 (P) and the -x-moving links of node d+1 (M); it is completed
   // as soon as node d+1 has been evaluated, so few link values stay live.
-  auto source_row = [&](auto store_c, int ys, RowAcc2<T, KX>& am, RowAcc2<T, KX>& ac, RowAcc2<T, KX>& ap,
-                        V (&ld)[3], E (&hld)[3]) {
+  auto source_row = [&](auto store_c, auto slot_c, int ys, RowAcc2<T, KX>& am, RowAcc2<T, KX>& ac,
+                        RowAcc2<T, KX>& ap) {
 #pragma clang fp contract(off)
     constexpr bool STORE = decltype(store_c)::value;
+    constexpr int SL = decltype(slot_c)::value;
+    const V(&cur)[3] = ring[SL];
+    const V(&prev)[3] = ring[(SL + 4) % 5];
+    const E(&hv)[3] = hring[SL];
     T dr[KX], ux[KX], uy[KX];
-    E hv[3];
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      prev[f] = cur[f];
-      cur[f] = ld[f];
-      hv[f] = hld[f];
-    }
 #pragma unroll
     for (int e = 0; e < KX; ++e) {
       dr[e] = C::dec(cur[0].v[e], 0);
       ux[e] = C::dec(cur[1].v[e], 1);
       uy[e] = C::dec(cur[2].v[e], 2);
     }
-    T of0[KX], oyp[KX], oym[KX];   // own links of node e
-    T pq[KX], ppp[KX], ppm[KX];    // P links of node e: (1,0)/4, (1,1), (1,-1)
-    T mq[KX], mmp[KX], mmm[KX];    // M links of node e: (-1,0)/4, (-1,1), (-1,-1)
-    auto complete = [&](int q, T Pq, T Ppp, T Ppm, T Mq, T Mmp, T Mmm) {
-      // row ys: rest, +-x
-      ac.r[q] += fma_t((T)4, Pq + Mq, of0[q]);
-      ac.mx[q] = fma_t((T)4, Pq - Mq, ac.mx[q]);
-      // row ys+1: +y, +x+y, -x+y
-      const T sp = fma_t((T)4, oyp[q], Ppp + Mmp);
-      ap.r[q] = sp;
-      ap.my[q] = sp;
-      ap.mx[q] = Ppp - Mmp;
-      // row ys-1: -y, +x-y, -x-y
-      const T sm = fma_t((T)4, oym[q], Ppm + Mmm);
-      am.r[q] += sm;
-      am.my[q] -= sm;
-      am.mx[q] += Ppm - Mmm;
-    };
+    Mom2<T> M[KX];
+    Send2<T> S[KX];
 #pragma unroll
     for (int e = 0; e < KX; ++e) {
-      Links2<T> L;
-      links2<T>(dr[e], ux[e], uy[e], rho_ref, L);
-      of0[e] = L.f0;
-      oyp[e] = L.qyp;
-      oym[e] = L.qym;
-      pq[e] = L.qxp;
-      ppp[e] = L.pp;
-      ppm[e] = L.pm;
-      mq[e] = L.qxm;
-      mmp[e] = L.mp;
-      mmm[e] = L.mm;
-      if (e >= 2) complete(e - 1, pq[e - 2], ppp[e - 2], ppm[e - 2], mq[e], mmp[e], mmm[e]);
+      moments2<T>(dr[e], ux[e], uy[e], rho_ref, M[e]);
+      S[e] = send2<T>(M[e]);
     }
-    Links2<T> H;
-    links2<T>(C::dec(hv[0], 0), C::dec(hv[1], 1), C::dec(hv[2], 2), rho_ref, H);  // meaningful on halo lanes only
-    load_row(ys + 3, ys + 3 <= y1, ld, hld);  // the slot just consumed takes row ys + 3
-    // links entering the lane's first node from the left and last node from the right
-    T in_q = dpp_from_left(pq[KX - 1]), in_pp = dpp_from_left(ppp[KX - 1]), in_pm = dpp_from_left(ppm[KX - 1]);
-    T in_mq = dpp_from_right(mq[0]), in_mp = dpp_from_right(mmp[0]), in_mm = dpp_from_right(mmm[0]);
+    // the node beside the segment (meaningful on the edge lanes only)
+    Mom2<T> HM;
+    moments2<T>(C::dec(hv[0], 0), C::dec(hv[1], 1), C::dec(hv[2], 2), rho_ref, HM);
+    const Send2<T> H = send2<T>(HM);
+    load_row(ys + 3, ys + 3 <= y1, ring[(SL + 3) % 5], hring[(SL + 3) % 5]);  // row ys - 2's slot
+    // what enters the lane's first node from the left and its last node from the right
+    T in_r0 = dpp_from_left(S[KX - 1].r0), in_r1 = dpp_from_left(S[KX - 1].r1),
+      in_r2 = dpp_from_left(S[KX - 1].c2);
+    T in_l0 = dpp_from_right(S[0].l0), in_l1 = dpp_from_right(S[0].l1), in_l2 = dpp_from_right(S[0].c2);
     if (lane == 0 && need_left) {
-      in_q = H.qxp;
-      in_pp = H.pp;
-      in_pm = H.pm;
+      in_r0 = H.r0;
+      in_r1 = H.r1;
+      in_r2 = H.c2;
     }
     if (lane == 63 && need_right) {
-      in_mq = H.qxm;
-      in_mp = H.mp;
-      in_mm = H.mm;
+      in_l0 = H.l0;
+      in_l1 = H.l1;
+      in_l2 = H.c2;
     }
-    if constexpr (KX == 1) {
-      complete(0, in_q, in_pp, in_pm, in_mq, in_mp, in_mm);
-    } else {
-      complete(0, in_q, in_pp, in_pm, mq[1], mmp[1], mmm[1]);
-      complete(KX - 1, pq[KX - 2], ppp[KX - 2], ppm[KX - 2], in_mq, in_mp, in_mm);
+#pragma unroll
+    for (int q = 0; q < KX; ++q) {
+      const T r0 = q > 0 ? S[q - 1].r0 : in_r0, r1 = q > 0 ? S[q - 1].r1 : in_r1, r2 = q > 0 ? S[q - 1].c2 : in_r2;
+      const T l0 = q < KX - 1 ? S[q + 1].l0 : in_l0, l1 = q < KX - 1 ? S[q + 1].l1 : in_l1,
+              l2 = q < KX - 1 ? S[q + 1].c2 : in_l2;
+      // the x pass of node q ...
+      const T t0 = fma_t((T)4, M[q].a, r0 + l0), u0 = r0 - l0;
+      const T t1 = fma_t((T)4, M[q].by, r1 + l1), u1 = r1 - l1;
+      const T t2 = fma_t((T)4, M[q].cyy, r2 + l2), u2 = r2 - l2;
+      // ... and the y pass: rows ys+1 (first touched here), ys and ys-1
+      const T pt = fma_t((T)1.5, t2, t0), pu = fma_t((T)1.5, u2, u0);
+      const T up = pt + t1, dn = pt - t1;
+      const T qup = pu + u1, qdn = pu - u1;
+      ap.r[q] = up;
+      ap.my[q] = up;
+      ap.mx[q] = qup;
+      ac.r[q] = fma_t((T)4, t0, ac.r[q]);
+      ac.mx[q] = fma_t((T)4, u0, ac.mx[q]);
+      am.r[q] += dn;
+      am.my[q] -= dn;
+      am.mx[q] += qdn;
     }
     const int yd = ys - 1;
     const int rb = STORE ? (int)((int64_t)lt.pitch * ywrap(yd) * EB) : 0;
@@ -283,21 +300,52 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src, typename C::elem* 
 
   using NoStore = std::integral_constant<bool, false>;
   using Store = std::integral_constant<bool, true>;
+  auto slot = [](auto k) { return std::integral_constant<int, decltype(k)::value>{}; };
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  using S2 = std::integral_constant<int, 2>;
+  using S3 = std::integral_constant<int, 3>;
+  using S4 = std::integral_constant<int, 4>;
   // source rows y0-1 .. y1 (y1 >= y0 + 1); the first two complete no row of
-  // the band
+  // the band. Accumulator roles rotate with period 3 and ring slots with
+  // period 5: fifteen rows per trip.
   load_row(y0 - 1, true, ring[0], hring[0]);
   load_row(y0, true, ring[1], hring[1]);
   load_row(y0 + 1, true, ring[2], hring[2]);
 #pragma unroll
-  for (int f = 0; f < 3; ++f) cur[f] = ring[0][f];
-  source_row(NoStore{}, y0 - 1, A0, A1, A2, ring[0], hring[0]);
-  source_row(NoStore{}, y0, A1, A2, A0, ring[1], hring[1]);
-  for (int ys = y0 + 1; ys <= y1; ys += 3) {
-    source_row(Store{}, ys, A2, A0, A1, ring[2], hring[2]);
+  for (int f = 0; f < 3; ++f) ring[4][f] = V{};  // the row before the first (never stored)
+  source_row(NoStore{}, slot(S0{}), y0 - 1, A0, A1, A2);
+  source_row(NoStore{}, slot(S1{}), y0, A1, A2, A0);
+  for (int ys = y0 + 1; ys <= y1; ys += 15) {
+    source_row(Store{}, S2{}, ys, A2, A0, A1);
     if (ys + 1 > y1) break;
-    source_row(Store{}, ys + 1, A0, A1, A2, ring[0], hring[0]);
+    source_row(Store{}, S3{}, ys + 1, A0, A1, A2);
     if (ys + 2 > y1) break;
-    source_row(Store{}, ys + 2, A1, A2, A0, ring[1], hring[1]);
+    source_row(Store{}, S4{}, ys + 2, A1, A2, A0);
+    if (ys + 3 > y1) break;
+    source_row(Store{}, S0{}, ys + 3, A2, A0, A1);
+    if (ys + 4 > y1) break;
+    source_row(Store{}, S1{}, ys + 4, A0, A1, A2);
+    if (ys + 5 > y1) break;
+    source_row(Store{}, S2{}, ys + 5, A1, A2, A0);
+    if (ys + 6 > y1) break;
+    source_row(Store{}, S3{}, ys + 6, A2, A0, A1);
+    if (ys + 7 > y1) break;
+    source_row(Store{}, S4{}, ys + 7, A0, A1, A2);
+    if (ys + 8 > y1) break;
+    source_row(Store{}, S0{}, ys + 8, A1, A2, A0);
+    if (ys + 9 > y1) break;
+    source_row(Store{}, S1{}, ys + 9, A2, A0, A1);
+    if (ys + 10 > y1) break;
+    source_row(Store{}, S2{}, ys + 10, A0, A1, A2);
+    if (ys + 11 > y1) break;
+    source_row(Store{}, S3{}, ys + 11, A1, A2, A0);
+    if (ys + 12 > y1) break;
+    source_row(Store{}, S4{}, ys + 12, A2, A0, A1);
+    if (ys + 13 > y1) break;
+    source_row(Store{}, S0{}, ys + 13, A0, A1, A2);
+    if (ys + 14 > y1) break;
+    source_row(Store{}, S1{}, ys + 14, A1, A2, A0);
   }
 }
 

@@ -482,10 +482,10 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
   // non-temporally, so it does not take L2 space from the rows that are read
   // twice. (The planes a tile shares with its z neighbours are read at the
   // start of one tile and the end of the other, too far apart for L2 to keep
-  // them, so they are loaded the same way.) Every wavefront issues both
-  // loads, one of them out of range. With
-  // a two-plane prefetch or padded rows the second set of loads does not fit
-  // in registers: all loads are then cached.
+  // them, so they are loaded the same way.) With a one-plane prefetch every
+  // wavefront issues both loads, one of them out of range; with a two-plane
+  // prefetch of 32-bit rows it branches on its (uniform) row role; padded
+  // rows and 16-bit rows at two planes are loaded cached.
   auto load_plane = [&](int z, bool valid, RawRow<C, KX>& b) {
     const int off = valid && mode != 3 ? row_off(z) : kOutOfRange;
     if constexpr (PF == 1 && !PADX) {
@@ -493,6 +493,20 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
       const int oc = once ? kOutOfRange : off, on = once ? off : kOutOfRange;
 #pragma unroll
       for (int f = 0; f < 4; ++f) b.f[f] = buf_or(buf_load<V>(rs[f], oc), buf_load<V, 2>(rs[f], on));
+    } else if constexpr (PF == 2 && !PADX && EB == 4) {
+      // with two planes in flight there are no registers for both load
+      // forms: the wavefront picks one with a branch that is uniform across
+      // it, so no wait for outstanding loads is needed where the paths join.
+      // (For 16-bit rows, whose loads are half as wide, non-temporal loads
+      // at this depth were slower: they stay cached.)
+      const bool once = __builtin_amdgcn_readfirstlane((int)(mode == 0 && wv >= 2 && wv <= rows - 1)) != 0;
+      if (once) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) b.f[f] = buf_load<V, 2>(rs[f], off);
+      } else {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) b.f[f] = buf_load<V>(rs[f], off);
+      }
     } else {
 #pragma unroll
       for (int f = 0; f < 4; ++f) b.f[f] = buf_load<V>(rs[f], off);
@@ -803,8 +817,10 @@ int fast_candidates(const Layout& L, const StepParams& p, int cus, FastShape* ou
   }
   for (int w : kFastW) {
     const int nyb = (nyo + w - 1) / w;
-    for (int mult : {1, 2}) {
-      int nzb = mult * cus / nyb;
+    // about one and two workgroups per CU, and a few z-chunk counts just
+    // below one per CU (fewer, longer chunks fill and drain less)
+    for (int eighths : {6, 7, 8, 16}) {
+      int nzb = eighths * cus / (8 * nyb);
       if (nzb < 1) nzb = 1;
       if (nzb > nzo) nzb = nzo;
       for (int pf : {1, 2}) {

@@ -265,8 +265,8 @@ int plan_candidates(const Layout& L, const StepParams& p, int cus, Plan* out, in
   int n = 0;
   out[n++] = plan_default(L, p, cus);
   if (fast_step_supported(L, p)) {
-    FastShape c[48];
-    const int m = fast_candidates(L, p, cus, c, 48);
+    FastShape c[80];
+    const int m = fast_candidates(L, p, cus, c, 80);
     for (int i = 0; i < m && n < max_out; ++i) {
       Plan pl;
       pl.kernel = 1 + c[i].kind;
@@ -642,8 +642,8 @@ int maclab_autotune(maclab_t h, int reps, double* best_ms) {
   StepParams p = make_params(h);
   const void* src = h->state[h->cur];
   void* dst = h->state[h->cur ^ 1];  // scratch output: the state is not advanced
-  Plan cand[64];
-  const int nc = plan_candidates(h->L, p, h->cus, cand, 64);
+  Plan cand[96];
+  const int nc = plan_candidates(h->L, p, h->cus, cand, 96);
   hipEvent_t e0, e1;
   HIP_TRY(h, hipEventCreate(&e0));
   hipError_t ee = hipEventCreate(&e1);
