@@ -38,6 +38,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "maclab_oracle.c")
 _LIB = os.path.join(_HERE, "libmaclab_oracle.so")
 _LIB_EXT = os.path.join(_HERE, "libmaclab_oracle_ext.so")
+_LIB_SAN = os.path.join(_HERE, "libmaclab_oracle_san.so")
+# A process started with MACLAB_ORACLE_LIB set uses that build of the oracle
+# by default (the sanitizer run of the pins does).
+_DEFAULT = os.environ.get("MACLAB_ORACLE_LIB") or None
 
 PERIODIC = 0
 FIXED = 1
@@ -46,12 +50,17 @@ PRESSURE = 3     # holds rho_b; velocity of the nearest interior node
 FACES = ("xlo", "xhi", "ylo", "yhi", "zlo", "zhi")
 
 
-def build(force: bool = False, extra_flags: tuple[str, ...] = (), out: str | None = None) -> str:
+SANITIZE_FLAGS = ("-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=all")
+
+
+def build(force: bool = False, extra_flags: tuple[str, ...] = (), out: str | None = None,
+          src: str | None = None) -> str:
     """Compiles the oracle with gcc (single thread, no FMA contraction)."""
-    out = out or _LIB
-    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+    out, src = out or _LIB, src or _SRC
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
         cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
-               *extra_flags, _SRC, "-o", out, "-lm"]
+               *extra_flags, src, "-o", out, "-lm"]
         subprocess.run(cmd, check=True)
     return out
 
@@ -62,6 +71,13 @@ def build_extended(force: bool = False) -> str:
     more bits, to separate the FP64 oracle's own rounding from a GPU path's
     in long runs."""
     return build(force, ('-DORACLE_REAL=long double',), _LIB_EXT)
+
+
+def build_sanitized(force: bool = False) -> str:
+    """The FP64 source with AddressSanitizer and UndefinedBehaviorSanitizer
+    (host code, gcc), every finding fatal. A process that loads it must
+    preload the sanitizer runtimes (see tests/test_oracle_sanitized.py)."""
+    return build(force, SANITIZE_FLAGS, _LIB_SAN)
 
 
 class _Problem(ctypes.Structure):
@@ -95,7 +111,7 @@ def use(path: str | None) -> str | None:
 
 
 def load(path: str | None = None) -> ctypes.CDLL:
-    path = path or _active or build()
+    path = path or _active or _DEFAULT or build()
     if path not in _libs:
         lib = ctypes.CDLL(path)
         lib.oracle_lattice.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), _dp]
