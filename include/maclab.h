@@ -257,7 +257,10 @@ int maclab_step_external(maclab_t h, const void* src, void* dst, int64_t step_in
  *           accumulator. Synchronises when dLdG is requested.
  * The force accumulator is summed per wavefront or workgroup in FP64 into
  * slots each owned by one of them, folded in a fixed order, so results are
- * reproducible. Stream-ordered; every buffer must stay valid until the
+ * reproducible. It lives in the handle on purpose, rather than as a partial
+ * buffer the caller passes to every step and reduces itself: the sum over a
+ * whole reverse sweep then has one fixed folding order, whatever the
+ * checkpoint schedule. Stream-ordered; every buffer must stay valid until the
  * stream reaches the call. */
 size_t maclab_adjoint_bytes(maclab_t h);
 int maclab_adjoint_seed(maclab_t h, const void* state_T, const double* dLdu, void* adj);
@@ -285,7 +288,10 @@ int maclab_get_adjoint_tiling(maclab_t h, int out[3]);
  * must be MACLAB_D2Q9; precision, rho_ref, seed and stream must match those
  * of lattice 0; the workspace fields are ignored) and lives in one caller-
  * owned workspace of maclab_batch_workspace_bytes (256-byte aligned device
- * memory; 0 means an invalid description).
+ * memory; 0 means an invalid description). A full maclab_config per
+ * lattice, rather than arrays of sizes and viscosities, is deliberate: each
+ * lattice keeps every per-lattice option of a single handle (its own dx,
+ * nu, body force and faces), validated by the same code as maclab_init.
  *  lattice:       a handle for lattice `index`, owned by the batch (NULL if
  *                 out of range). Use it with maclab_set_bc, set_fields,
  *                 get_fields, diagnostics, params, save_state and load_state
