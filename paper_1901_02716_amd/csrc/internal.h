@@ -32,6 +32,11 @@ struct Layout {
   size_t workspace_bytes = 0;
 };
 
+// A state buffer at least this large does not fit in the device's 256 MB
+// last-level (memory-side) cache: what one step writes is evicted before the
+// next step reads it, so the D2Q9 step streams its stores past the caches.
+constexpr size_t kStreamStoreBytes = size_t(256) << 20;
+
 constexpr int kDiagBlocks = 1024;  // partial sums of the diagnostics reduction
 constexpr int kDiagValues = 8;     // M, Px, Py, Pz, E, max|u~|, non-finite, pad
 
@@ -116,8 +121,11 @@ struct Lattice2D {
 };
 // A batch step: work item {lattice, x0, y0, y1} of a device table, one
 // wavefront each, all lattices in one launch (every pitch a multiple of kx).
+// stream_stores: non-temporal stores (a state buffer of kStreamStoreBytes or
+// more).
 hipError_t launch_step_fast2d_items(int precision, int kx, const void* src, void* dst, const Lattice2D* lat,
-                                    const int4* items, int nitems, double rho_ref, uint32_t sr_key, hipStream_t s);
+                                    const int4* items, int nitems, double rho_ref, uint32_t sr_key,
+                                    bool stream_stores, hipStream_t s);
 
 // Reverse mode (kernels_adjoint.hip). Adjoint buffers hold (Rbar, Mbar) in
 // the compute type, d + 1 planes of `plane` elements.

@@ -194,7 +194,7 @@ int make_layout(const maclab_config* c, Layout* L, std::string* why) {
 }
 
 StepParams make_params(const maclab_t h) {
-  StepParams p;
+  StepParams p{};
   p.nx = h->L.nx;
   p.ny = h->L.ny;
   p.nz = h->L.nz;
@@ -1086,7 +1086,7 @@ void batch_advance(maclab_batch_t b, int64_t n) {
 int batch_launch(maclab_batch_t b, hipStream_t s, int cur, int64_t step) {
   const uint32_t key = sr_key(b->seed, (uint64_t)step);
   BHIP_TRY(b, launch_step_fast2d_items(b->precision, b->kx, b->state[cur], b->state[cur ^ 1], b->table, b->items,
-                                       b->nitems, b->rho_ref, key, s));
+                                       b->nitems, b->rho_ref, key, b->state_bytes >= kStreamStoreBytes, s));
   return MACLAB_OK;
 }
 
