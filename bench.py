@@ -607,7 +607,7 @@ def main(argv=None):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "copy_ceiling": {"kernel": "maclab_copy: the state buffer copied back and forth (non-temporal "
-                                   "16-byte loads and stores)",
+                                   "16-byte loads, device-scope stores)",
                          "bytes_per_copy": info["copy_bytes"], "ms_per_copy": round(info["copy_ms"], 5),
                          "gbs": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),
                          "step_frac_of_copy": round(achieved / copy_gbs, 4)},

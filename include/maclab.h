@@ -336,8 +336,9 @@ const char* maclab_batch_last_error(maclab_batch_t b);
 
 /* Calibration: copies `bytes` from src to dst (caller device memory, 16-byte
  * aligned, not overlapping; bytes a multiple of 16) on the handle's stream
- * with non-temporal 16-byte loads and stores (the fastest copy form measured
- * on the device). Copying a state buffer back and forth moves the bytes of a step
+ * with non-temporal 16-byte loads and device-scope (write-through) stores,
+ * the access forms of the step kernels and the fastest copy form measured on
+ * the device. Copying a state buffer back and forth moves the bytes of a step
  * without its arithmetic, which gives the memory rate a step can reach on
  * the device. Asynchronous. MACLAB_EINVAL for a NULL or misaligned pointer
  * or a size that is not a multiple of 16. */

@@ -288,6 +288,12 @@ struct BufIO<16> {
   __device__ static void store(U v, buf_t r, int off) { __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, AUX); }
 };
 
+// Cache-policy words of buffer loads and stores (gfx950): sc0 = 1, nt = 2,
+// sc1 = 16. Non-temporal (nt) accesses stream past the caches; a
+// device-scope store (sc1) writes through L2 to memory.
+constexpr int kStoreStream = 2;
+constexpr int kStoreDevice = 16;
+
 // Loads / stores a trivially copyable V (2, 4, 8 or 16 bytes) at a byte offset;
 // AUX is the cache-policy word (2: non-temporal).
 template <class V, int AUX = 0>

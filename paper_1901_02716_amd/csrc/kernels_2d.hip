@@ -117,11 +117,14 @@ struct Occupancy2D {
 // at least 128 bytes (the row pitch), so a lane moves its KX nodes with one
 // vector access per field.
 //
-// NT: stores stream past the caches, for a state buffer larger than the
-// device's memory-side cache, where cached stores only evict what the step
-// still has to read (the 512-cavity batch step: 325 -> 283 us). Otherwise
-// they stay cached, so that the next step reads a lattice that fits in that
-// cache back from it (a 2048^2 FP32 cavity: 16.3 us cached, 24.8 streamed).
+// NT: stores stream past the caches (non-temporal), for a state buffer
+// larger than the device's memory-side cache, where stores that stay in the
+// caches only evict what the step still has to read (the 512-cavity batch
+// step: 325 us cached, 283 us streamed, 321 us device-scope). Otherwise they
+// are device-scope stores (sc1), which write through L2 and leave the new
+// state in the memory-side cache for the next step, with nothing dirty in L2
+// for the end of the kernel to write back (1024^2 FP64 cavity: 10.3 us
+// cached, 8.9 us device-scope; 2048^2 FP32: 16.2, 15.1; 24.8 streamed).
 template <class C, int KX, bool NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy2D<C, KX>::value)))
 void step_d2q9_fast(const typename C::elem* __restrict__ src, typename C::elem* __restrict__ dst, Fast2DParams p) {
@@ -301,7 +304,7 @@ void step_d2q9_fast(const typename C::elem* __restrict__ src, typename C::elem* 
     }
     const int off = STORE && xb < lt.nx ? rb + xb * EB : kOutOfRange;
 #pragma unroll
-    for (int f = 0; f < 3; ++f) buf_store<V, NT ? 2 : 0>(o[f], rd[f], off);
+    for (int f = 0; f < 3; ++f) buf_store<V, NT ? kStoreStream : kStoreDevice>(o[f], rd[f], off);
   };
 
   using NoStore = std::integral_constant<bool, false>;

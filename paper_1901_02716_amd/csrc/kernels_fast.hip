@@ -584,9 +584,13 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
       }
     }
     const int off = STORE && out_row ? row_off(zd) : kOutOfRange;
-    // the new state is not read again in this step: stream it past the caches
+    // the new state is not read again in this step. Device-scope stores (sc1)
+    // write through L2, so nothing of the new state is left dirty there for
+    // the end of the kernel to write back, and the memory-side cache may keep
+    // what the next step reads first: FP32 256^3 97.9 -> 93.3 us against
+    // non-temporal stores (a plain copy of the same bytes: 85.5 -> 79.7 us).
 #pragma unroll
-    for (int f = 0; f < 4; ++f) buf_store<V, 2>(o[f], rd[f], off);
+    for (int f = 0; f < 4; ++f) buf_store<V, kStoreDevice>(o[f], rd[f], off);
   };
 
   // Source planes z0-1 .. z1 (z1 >= z0 + 1); the first two complete no plane

@@ -431,16 +431,23 @@ hipError_t launch_diagnostics(const Layout& L, const void* state, double rho_ref
   return hipGetLastError();
 }
 
-// Streaming copy of n16 16-byte words: non-temporal 16-byte loads and stores
-// (the fastest copy form measured on the device; the step kernels store this
-// way and load most rows this way). It moves the bytes of a step with none
-// of its arithmetic, so its rate is the memory rate a step can reach.
-__global__ void stream_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16) {
+// Streaming copy in the access forms of the step kernels, to measure the
+// memory rate a step can reach: 16-byte non-temporal loads and device-scope
+// (sc1) stores, the fastest copy of a state buffer measured on the device
+// (a 268 MB buffer back and forth: 79.7 us with four workgroups of 256 per
+// CU, 85.5 us with non-temporal stores, 89.6 us with 8192 workgroups). It
+// moves the bytes of a step with none of its arithmetic. blockIdx.y selects
+// a chunk of at most kCopyChunk bytes, which one buffer resource addresses.
+constexpr int64_t kCopyChunk = int64_t(1) << 30;
+__global__ void stream_copy_kernel(const char* __restrict__ src, char* __restrict__ dst, int64_t bytes) {
   typedef uint32_t w4 __attribute__((ext_vector_type(4)));
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
-    __builtin_nontemporal_store(__builtin_nontemporal_load(reinterpret_cast<const w4*>(src + i)),
-                                reinterpret_cast<w4*>(dst + i));
+  const int64_t base = (int64_t)blockIdx.y * kCopyChunk;
+  const int64_t left = bytes - base;
+  const int len = (int)(left < kCopyChunk ? left : kCopyChunk);
+  const buf_t rs = make_buf(src + base, len), rd = make_buf(dst + base, len);
+  const int stride = (int)(gridDim.x * blockDim.x) * 16;
+  for (int off = (int)(blockIdx.x * blockDim.x + threadIdx.x) * 16; off < len; off += stride)
+    buf_store<w4, kStoreDevice>(buf_load<w4, kStoreStream>(rs, off), rd, off);
 }
 
 hipError_t launch_residual(const Layout& L, const void* prev, const void* cur, double* partials, double* result,
@@ -478,11 +485,13 @@ hipError_t launch_touch(const void* buf, size_t bytes, uint32_t* sink, uint32_t 
 }
 
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
-  const int64_t n16 = (int64_t)(bytes / 16);
-  if (n16 == 0) return hipSuccess;
-  const int64_t want = (n16 + 255) / 256;
-  const unsigned blocks = (unsigned)(want < 8192 ? want : 8192);
-  hipLaunchKernelGGL(stream_copy_kernel, dim3(blocks), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, n16);
+  if (bytes == 0) return hipSuccess;
+  if (bytes % 16) return hipErrorInvalidValue;
+  const int64_t chunks = ((int64_t)bytes + kCopyChunk - 1) / kCopyChunk;
+  const int64_t want = ((int64_t)(bytes < (size_t)kCopyChunk ? bytes : (size_t)kCopyChunk) / 16 + 255) / 256;
+  const unsigned blocks = (unsigned)(want < 1024 ? want : 1024);
+  hipLaunchKernelGGL(stream_copy_kernel, dim3(blocks, (unsigned)chunks), dim3(256), 0, s, (const char*)src,
+                     (char*)dst, (int64_t)bytes);
   return hipGetLastError();
 }
 

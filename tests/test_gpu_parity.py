@@ -674,6 +674,16 @@ def test_copy_calibration_kernel():
     for bad in ((a[1:], b, 16), (a, a[16:], 1024), (a, b, 17)):
         with pytest.raises(MaclabError):
             sim.copy(*bad)
+    # past one 1 GiB chunk (the copy addresses each chunk with its own buffer resource)
+    big = (1 << 30) + 4096 + 16
+    gd = torch.Generator(device=sim.device).manual_seed(6)
+    a2 = torch.randint(0, 256, (big,), dtype=torch.uint8, device=sim.device, generator=gd)
+    b2 = torch.zeros_like(a2)
+    sim.copy(a2, b2)
+    torch.cuda.synchronize()
+    assert torch.equal(a2, b2)
+    del a2, b2
+    torch.cuda.empty_cache()
 
 
 def test_zero_steps_and_smallest_walled_lattices():
