@@ -658,13 +658,14 @@ int maclab_autotune(maclab_t h, int reps, double* best_ms) {
     if ((err = launch_plan(h->L, p, cand[i], src, dst, h->stream)) != hipSuccess) break;  // warm-up
     double total = 0;
     for (int r = 0; r < reps && err == hipSuccess; ++r) {
-      // A time step reads a source that the step before wrote with
-      // non-temporal stores, which it finds in no cache. Launches repeated
-      // from one source would find part of it in the last-level cache, and
-      // favour tilings whose loads keep data there; reading the spare buffer
-      // first (untimed) evicts the source.
-      if ((err = launch_touch(dst, h->L.state_bytes, (uint32_t*)h->partials, 0x9e3779b9u, h->stream)) != hipSuccess)
-        break;
+      // A time step reads a source that the step before has just written
+      // with write-through stores, part of which the memory-side cache may
+      // still hold, and nothing else. Launches repeated from one source would
+      // find other data there (the source they read before). So before each
+      // timed launch the source is copied to the spare buffer and back
+      // (untimed; the same bytes, stored the way a step stores them).
+      if ((err = launch_stream_copy(src, dst, h->L.state_bytes, h->stream)) != hipSuccess) break;
+      if ((err = launch_stream_copy(dst, h->state[h->cur], h->L.state_bytes, h->stream)) != hipSuccess) break;
       if ((err = hipEventRecord(e0, h->stream)) != hipSuccess) break;
       if ((err = launch_plan(h->L, p, cand[i], src, dst, h->stream)) != hipSuccess) break;
       if ((err = hipEventRecord(e1, h->stream)) != hipSuccess) break;
