@@ -33,9 +33,11 @@ their results are stored in compact form:
   oracle built in x87 extended precision (oracle.run_extended).
 * ``batch512_stable.npz`` -- the three largest cavities of the 512-cavity
   draw (seed 4) whose lattice Reynolds number U dx / nu is at most 2.5,
-  2000 steps each: diagnostics and every 4th node per axis of rho and u.
+  2000 steps each: diagnostics and every 4th node per axis of rho and u;
+  ``batch512_stable_10000.npz`` the same after 10000 steps
+  (``batch512 10000``).
 
-Usage: python tests/golden/make_references.py {cube64,cube64_re400,cavity1024,cavity1024_extended,adjoint512 [workers],batch512}
+Usage: python tests/golden/make_references.py {cube64,cube64_re400,cavity1024,cavity1024_extended,adjoint512 [workers],batch512 [steps]}
 """
 from __future__ import annotations
 
@@ -227,15 +229,16 @@ def adjoint512(workers=6):
     json.dump(out, open(os.path.join(HERE, "adjoint512_fd.json"), "w"), indent=1)
 
 
-def _batch_run(i):
+def _batch_run(args):
+    i, steps = args
     N, Re, U = workloads.batch_draw()[i]
     case = workloads.cavity_2d(n=N, Re=Re, U=U)
     p = problem(case)
-    rho, u = oracle.run(p, case.rho, case.u, 2000)
+    rho, u = oracle.run(p, case.rho, case.u, steps)
     return i, oracle.diagnostics(p, rho, u), rho[0, ::4, ::4], u[:, 0, ::4, ::4]
 
 
-def batch512(workers=3):
+def batch512(steps=2000, workers=3):
     from multiprocessing import Pool
 
     draws = workloads.batch_draw()
@@ -243,13 +246,14 @@ def batch512(workers=3):
     idx = [i for _, i in stable]
     t0 = time.time()
     with Pool(workers) as pool:
-        res = pool.map(_batch_run, idx)
-    out = {"index": np.array(idx), "steps": 2000, "stride": 4, "seconds": time.time() - t0}
+        res = pool.map(_batch_run, [(i, steps) for i in idx])
+    out = {"index": np.array(idx), "steps": steps, "stride": 4, "seconds": time.time() - t0}
     for i, d, r, u in res:
         out[f"diag_{i}"] = d
         out[f"rho_sub_{i}"] = r
         out[f"u_sub_{i}"] = u
-    np.savez_compressed(os.path.join(HERE, "batch512_stable.npz"), **out)
+    name = "batch512_stable.npz" if steps == 2000 else f"batch512_stable_{steps}.npz"
+    np.savez_compressed(os.path.join(HERE, name), **out)
 
 
 if __name__ == "__main__":
@@ -257,7 +261,7 @@ if __name__ == "__main__":
     if sys.argv[1] == "adjoint512":
         adjoint512(int(sys.argv[2]) if len(sys.argv) > 2 else 6)
     elif sys.argv[1] == "batch512":
-        batch512()
+        batch512(int(sys.argv[2]) if len(sys.argv) > 2 else 2000)
     elif sys.argv[1] == "cavity1024_extended":
         cavity1024_extended()
     else:
