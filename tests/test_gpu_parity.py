@@ -230,6 +230,8 @@ def _storage_unit(x, precision, field):
     ("cube256_fp32", lambda: workloads.cavity_3d(n=256, Re=400.0, U=0.1), "fp32", 1e-5),
     ("cavity1024_fp64", lambda: workloads.cavity_2d(n=1024, Re=1000.0, U=0.1), "fp64", 1e-12),
     ("cavity1024_fp32", lambda: workloads.cavity_2d(n=1024, Re=1000.0, U=0.1), "fp32", 1e-5),
+    # 403 MB per state buffer: the D2Q9 step with non-temporal stores
+    ("cavity4096_fp64", lambda: workloads.cavity_2d(n=4096, Re=1000.0, U=0.1), "fp64", 1e-12),
     ("periodic512_fp32", lambda: workloads.adjoint_case()[0], "fp32", 1e-5),
     ("cube256_s16", lambda: workloads.cavity_3d(n=256, Re=400.0, U=0.1), "s16", 2e-3),
     ("cube256_hilo", lambda: workloads.cavity_3d(n=256, Re=400.0, U=0.1), "hilo", 2e-3),
