@@ -637,9 +637,8 @@ __global__ __launch_bounds__(64 * (W + 2)) void step_d3q19_fast(const typename C
 // that reach it. Link values and the order of every sum are those of the
 // exchange kernel above, so both kernels give the same bits.
 template <class C, int KX, int S>
-__device__ __forceinline__ void neighbour_row(const RowData<KX>& b, float rho_ref, int d_unused, PlaneAcc<KX>& am,
+__device__ __forceinline__ void neighbour_row(const RowData<KX>& b, float rho_ref, PlaneAcc<KX>& am,
                                               PlaneAcc<KX>& ac, PlaneAcc<KX>& ap) {
-  (void)d_unused;
   float h[KX], ep[KX], em[KX], vp[KX], vm[KX];
 #pragma unroll
   for (int e = 0; e < KX; ++e) {
@@ -718,9 +717,9 @@ __global__ __launch_bounds__(64 * NWV) void step_d3q19_indep(const typename C::e
       if (zs < z1) load(y, zs + 1, own);
       own_row_links<KX>(f0, hzp, hzm, hxp, p0p, p0m, hxm, m0p, m0m, am, ac, ap);
     }
-    neighbour_row<C, KX, 1>(below, p.rho_ref, 0, am, ac, ap);
+    neighbour_row<C, KX, 1>(below, p.rho_ref, am, ac, ap);
     if (zs < z1) load(yb, zs + 1, below);
-    neighbour_row<C, KX, -1>(above, p.rho_ref, 0, am, ac, ap);
+    neighbour_row<C, KX, -1>(above, p.rho_ref, am, ac, ap);
     if (zs < z1) load(ya, zs + 1, above);
     const int zd = zs - 1;
     if (zd >= z0) {
