@@ -16,7 +16,9 @@ Output: one JSON line with
     back and forth, the memory rate a step can reach on this device;
   - `cpu_baseline`: the FP64 CPU oracle timed on a bounded sample of the
     same workload, one single-threaded oracle process per host core (at
-    most 16), each on its own copy;
+    most 16), each on its own copy; `small_configs` beside it: the oracle on
+    one core over the whole 64^2 Taylor-Green run and a 10-step window of
+    the 1024^2 cavity;
   - `variants` (S16, HILO), `adjoint` (the 512^2 D2Q9 reverse mode against
     the forward), `batch` (512 D2Q9 cavities in one launch per step against
     one launch per cavity), `launch_bound` (a 64^2 lattice),
@@ -443,6 +445,46 @@ def _oracle_steps(workload: str, steps: int, core: int = -1) -> float:
     return time.perf_counter() - t0
 
 
+def _oracle_small(kind: str, steps: int, core: int) -> float:
+    """Seconds the FP64 oracle takes for `steps` steps of a small config
+    (`tgv64`: the 64^2 Taylor-Green vortex; `cavity1024`: the 1024^2 cavity
+    from rest), pinned to host core `core`."""
+    os.sched_setaffinity(0, {core})
+    import oracle
+    from paper_1901_02716_amd import workloads
+
+    if kind == "tgv64":
+        case = workloads.taylor_green(64, 0.01, 0.01, e=oracle.particle_speed(0.01, 1.0 / 64))
+    else:
+        case = workloads.cavity_2d(n=1024, Re=1000.0, U=0.1)
+    p = oracle.Problem(case.q, case.n, case.dx, case.nu)
+    for face, (rb, ub) in case.fixed.items():
+        p.set_fixed(face, rb, ub)
+    t0 = time.perf_counter()
+    oracle.run(p, case.rho, case.u, steps)
+    return time.perf_counter() - t0
+
+
+def oracle_configs(core: int) -> dict:
+    """The FP64 oracle timed on the small configs, one single-threaded child
+    process each on one host core: the whole 1000-step 64^2 Taylor-Green run
+    and 10 steps of the 1024^2 cavity (a window of its 50000-step run)."""
+    import subprocess
+
+    out = {}
+    for kind, steps, nodes in (("tgv64", 1000, 64 * 64), ("cavity1024", 10, 1022 * 1022)):
+        code = (f"import sys; sys.path.insert(0, {ROOT!r}); import bench; "
+                f"print(bench._oracle_small({kind!r}, {steps}, {core}))")
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                           env=dict(os.environ, OMP_NUM_THREADS="1"))
+        if r.returncode != 0:
+            raise RuntimeError(f"oracle worker failed with status {r.returncode}")
+        sec = float(r.stdout.strip().splitlines()[-1])
+        out[kind] = {"steps": steps, "seconds": round(sec, 3), "mlups": round(nodes * steps / sec / 1e6, 3),
+                     "cores": 1}
+    return out
+
+
 def host_cores() -> list:
     """Host cores to run the oracle on: those this process may use, at most
     16 (the host share of one GPU)."""
@@ -580,6 +622,8 @@ def main(argv=None):
                          f"updates; slowest {cdt:.1f} s, fastest {min(csecs):.1f} s; one process alone: "
                          f"about {args.cpu_steps * lu / min(csecs) / 1e6:.2f} MLUPS)",
                "cpu_model": cpu_model(), "pinned_cores": cores}
+        if extras:
+            cpu["small_configs"] = oracle_configs(cores[0])
 
     if args.profile_copy_mib > 0:
         n = args.profile_copy_mib << 20
