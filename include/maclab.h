@@ -301,7 +301,8 @@ int maclab_get_adjoint_tiling(maclab_t h, int out[3]);
  *  step:          n steps of every lattice (Eqs. (4)-(5) with each
  *                 lattice's faces and force): one launch per step over a
  *                 table of work items {lattice, x-segment of 64*kx nodes,
- *                 band of `rows` rows}, largest first. Runs of
+ *                 band of `rows` rows}: lattices largest first, the items
+ *                 of one lattice in row order. Runs of
  *                 steps_per_graph steps are captured once in a HIP graph
  *                 and replayed on a private stream ordered after and before
  *                 the caller's stream (not for MACLAB_S16, whose rounding is

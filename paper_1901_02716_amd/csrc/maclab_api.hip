@@ -995,7 +995,18 @@ int batch_plan(maclab_batch_t b, int kx, int rows, std::vector<Lattice2D>* table
   if (rows < kBatchRowsMin) return bfail(b, MACLAB_EINVAL, "rows per work item must be >= %d", kBatchRowsMin);
   table->assign(b->count, Lattice2D{});
   items->clear();
-  for (int i = 0; i < b->count; ++i) {
+  // Lattices largest first, so the tail of a launch is made of small ones;
+  // the items of one lattice in row order (bands, and the x-segments of a
+  // band), so that neighbouring bands run at about the same time on one XCD
+  // and the rows each reads beside its own come from that XCD's L2. (Sorting
+  // the items themselves by size scattered the bands of a lattice, and a
+  // batch step then read 1.39 times the bytes of its fields.)
+  std::vector<int> order(b->count);
+  for (int i = 0; i < b->count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    return b->lat[a]->L.nx * b->lat[a]->L.ny > b->lat[c]->L.nx * b->lat[c]->L.ny;
+  });
+  for (int i : order) {
     maclab_s* h = b->lat[i];
     const int rc = check_faces(h);
     if (rc) return bfail(b, rc, "lattice %d: %s", i, h->err.c_str());
@@ -1025,11 +1036,6 @@ int batch_plan(maclab_batch_t b, int kx, int rows, std::vector<Lattice2D>* table
     }
   }
   if ((int64_t)items->size() > b->max_items) return bfail(b, MACLAB_EINVAL, "too many work items for the workspace");
-  // the largest items first, so the tail of a launch is made of small ones
-  std::stable_sort(items->begin(), items->end(), [&](const int4& a, const int4& c) {
-    const int64_t wa = std::min(64 * kx, (*table)[a.x].nx - a.y), wc = std::min(64 * kx, (*table)[c.x].nx - c.y);
-    return (int64_t)(a.w - a.z) * wa > (int64_t)(c.w - c.z) * wc;
-  });
   return MACLAB_OK;
 }
 
